@@ -1,0 +1,251 @@
+"""Seeded synthetic workloads: problem descriptions and initial macroscopic fields.
+
+This module is the only code shared by the HIP path's tests/benchmark and the
+CPU oracle's tests.  It holds no arithmetic of the lattice Boltzmann method
+itself (no equilibrium, moments or convection): it produces plain numbers —
+grid sizes, radii, relaxation time, time step, boundary descriptions and the
+initial fields rho, u_r, u_theta, T on the nodes — and seeded random arrays.
+
+The problems are the annulus setups of the paper's validation section (Sec. III)
+rewritten as synthetic initial-value problems:
+
+* ``rotation``: rotational flow between coaxial cylinders (Sec. III.A), rigid
+  rotation u_theta = 0.5 r at rho = 1, T = 1; ``rotation_hydrostatic`` adds the
+  radial pressure balance rho = exp(omega^2 (r^2 - R1^2) / 2T).
+* ``shock_tube``: radial Riemann problem (as in Sec. III.B, at laboratory radii).
+* ``richtmyer_meshkov``: outward shock from Rankine-Hugoniot (Eq. Hugoniot)
+  meeting a perturbed material interface (Sec. III.C).
+* ``kelvin_helmholtz``: tanh shear layer with a radial-velocity perturbation
+  (Eqs. KH_initial, KH_perturbation).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+# Radial boundary kinds (Sec. II.C, radial boundary condition).
+WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
+
+#: largest speed of the discrete velocity set (v_4 of Sec. II.A); used only by
+#: the time-step rule below.
+MAX_SPEED = 4.49
+
+
+@dataclass(frozen=True)
+class Problem:
+    name: str
+    nr: int
+    nth: int
+    r1: float
+    r2: float
+    tau: float
+    dt: float
+    steps: int
+    bc_kind: tuple = (WALL, WALL)
+    bc_par: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
+    params: dict = field(default_factory=dict, compare=False, hash=False)
+
+    @property
+    def dr(self) -> float:
+        return (self.r2 - self.r1) / (self.nr - 1)
+
+    @property
+    def dth(self) -> float:
+        return 2.0 * math.pi / self.nth
+
+    @property
+    def nodes(self) -> int:
+        return self.nr * self.nth
+
+
+def cfl_dt(nr: int, nth: int, r1: float, r2: float, cfl: float = 0.3) -> float:
+    """dt = cfl * min(dr, R1 dtheta) / max|v| (the configs' time-step rule)."""
+    dr = (r2 - r1) / (nr - 1)
+    dth = 2.0 * math.pi / nth
+    return cfl * min(dr, r1 * dth) / MAX_SPEED
+
+
+def node_coords(nr: int, nth: int, r1: float, r2: float):
+    """r_i = R1 + i dr, theta_j = (j+1) dtheta (Sec. II.C node placement,
+    0-based); returns 2-D arrays R[i, j], TH[i, j]."""
+    dr = (r2 - r1) / (nr - 1)
+    dth = 2.0 * math.pi / nth
+    r = r1 + dr * np.arange(nr, dtype=np.float64)
+    th = dth * (np.arange(nth, dtype=np.float64) + 1.0)
+    return np.meshgrid(r, th, indexing="ij")
+
+
+def hugoniot(rho0: float, u0: float, P0: float, D: float, gamma: float = 2.0):
+    """Post-shock (rho_H, u_H, P_H) behind a shock of speed D moving into the
+    state (rho0, u0, P0); the solution of Eq. Hugoniot for an ideal gas with
+    E = P / ((gamma - 1) rho)."""
+    c0 = math.sqrt(gamma * P0 / rho0)
+    M = (D - u0) / c0
+    ratio = (gamma + 1.0) * M * M / ((gamma - 1.0) * M * M + 2.0)
+    rhoH = rho0 * ratio
+    uH = D - (D - u0) * rho0 / rhoH
+    PH = P0 + rho0 * (D - u0) * (uH - u0)
+    return rhoH, uH, PH
+
+
+# ---------------------------------------------------------------------------
+# Problem definitions.  Each returns (Problem, fields) where fields is a dict of
+# float64 arrays rho, ur, ut, T of shape (nr, nth).
+
+def rotation(nr=64, nth=128, steps=200, hydrostatic=False, omega=0.5, tau=1e-4):
+    r1, r2 = 1.0, 2.0
+    dt = cfl_dt(nr, nth, r1, r2)
+    P = Problem("rotation_hydrostatic" if hydrostatic else "rotation", nr, nth, r1, r2, tau, dt,
+                steps, (WALL, WALL), ((omega, 0, 0, 0), (omega, 0, 0, 0)),
+                {"omega": omega})
+    R, TH = node_coords(nr, nth, r1, r2)
+    T = np.ones_like(R)
+    rho = np.exp(omega ** 2 * (R ** 2 - r1 ** 2) / 2.0) if hydrostatic else np.ones_like(R)
+    return P, dict(rho=rho, ur=np.zeros_like(R), ut=omega * R, T=T)
+
+
+def shock_tube(nr=512, nth=1024, steps=2000, tau=2e-5, noise=1e-6, seed=0):
+    r1, r2 = 0.2, 1.2
+    dt = cfl_dt(nr, nth, r1, r2)
+    P = Problem("shock_tube", nr, nth, r1, r2, tau, dt, steps, (WALL, WALL),
+                ((0, 0, 0, 0), (0, 0, 0, 0)), {"seed": seed, "noise": noise})
+    R, TH = node_coords(nr, nth, r1, r2)
+    inner = R < 0.7
+    rho = np.where(inner, 1.0, 0.125)
+    T = np.where(inner, 1.0, 0.8)
+    rng = np.random.default_rng(seed)
+    rho = rho + noise * rng.uniform(-1.0, 1.0, size=R.shape)
+    return P, dict(rho=rho, ur=np.zeros_like(R), ut=np.zeros_like(R), T=T)
+
+
+RM_MODES = tuple(range(4, 17))
+
+
+def rm_amplitudes(seed=1) -> np.ndarray:
+    """Interface amplitudes a_k ~ U(0, 5e-3) for k = 4..16 (seeded)."""
+    return np.random.default_rng(seed).uniform(0.0, 5e-3, len(RM_MODES))
+
+
+def richtmyer_meshkov(nr=2048, nth=4096, steps=5000, tau=2e-5, amps=None, seed=1,
+                      width=0.005, pressure_balance=False, xp=np):
+    """Shock of Mach 2 (gamma = 2) at r = 0.8 moving outward into rho = 1,
+    T = 1; interface r_I = 1.2 + sum_k a_k cos(k theta) between rho = 1 and
+    rho = 3, smoothed as a tanh of width ``width``.  With pressure_balance the
+    outer medium has T = 1/3 (P = 1 on both sides, as in the paper's runs);
+    otherwise T = 1 on both sides.  ``amps`` may be a torch tensor (then
+    xp=torch) so that the fields are differentiable in a_k."""
+    r1, r2 = 0.2, 2.2
+    dt = cfl_dt(nr, nth, r1, r2)
+    c0 = math.sqrt(2.0)
+    D = 2.0 * c0
+    rhoH, uH, PH = hugoniot(1.0, 0.0, 1.0, D)
+    TH_ = PH / rhoH
+    P = Problem("richtmyer_meshkov", nr, nth, r1, r2, tau, dt, steps, (INFLOW, WALL),
+                ((rhoH, uH, 0.0, TH_), (0, 0, 0, 0)),
+                {"seed": seed, "width": width, "pressure_balance": pressure_balance})
+    if amps is None:
+        amps = rm_amplitudes(seed)
+    R, TH = node_coords(nr, nth, r1, r2)
+    if xp is not np:
+        import torch
+        R = torch.as_tensor(R, dtype=torch.float64, device=amps.device)
+        TH = torch.as_tensor(TH, dtype=torch.float64, device=amps.device)
+    rI = 1.2
+    for a, k in zip(amps, RM_MODES):
+        rI = rI + a * xp.cos(k * TH)
+    s = 0.5 * (1.0 + xp.tanh((R - rI) / width))
+    rho_out, T_out = 3.0, (1.0 / 3.0 if pressure_balance else 1.0)
+    shocked = R < 0.8
+    one = xp.ones_like(R)
+    rho = xp.where(shocked, rhoH * one, 1.0 + (rho_out - 1.0) * s)
+    T = xp.where(shocked, TH_ * one, 1.0 + (T_out - 1.0) * s)
+    ur = xp.where(shocked, uH * one, 0.0 * one)
+    return P, dict(rho=rho, ur=ur, ut=0.0 * one, T=T)
+
+
+def rm_interface_sensitivity(P: Problem, amps) -> np.ndarray:
+    """d rho_0 / d a_k of the Richtmyer-Meshkov initial density, shape
+    (13, nr, nth); u and T have no dependence on a_k when T is uniform."""
+    R, TH = node_coords(P.nr, P.nth, P.r1, P.r2)
+    W = P.params["width"]
+    rI = 1.2 + sum(a * np.cos(k * TH) for a, k in zip(amps, RM_MODES))
+    x = (R - rI) / W
+    ds_drI = -0.5 / W / np.cosh(x) ** 2
+    out = np.empty((len(RM_MODES), P.nr, P.nth))
+    for n, k in enumerate(RM_MODES):
+        out[n] = np.where(R < 0.8, 0.0, 2.0 * ds_drI * np.cos(k * TH))
+    return out
+
+
+def kelvin_helmholtz(nr=4096, nth=8192, steps=1000, tau=1e-5, warmup=50):
+    """u_theta = 0.5 tanh((r-1)/0.01), u_r = 1e-3 sin(8 theta) exp(-((r-1)/0.02)^2),
+    rho = 1, T = 1 on r in [0.5, 1.5]; walls turning with the flow at r = 0.5, 1.5."""
+    r1, r2 = 0.5, 1.5
+    dt = cfl_dt(nr, nth, r1, r2)
+    w_in = 0.5 * math.tanh((r1 - 1.0) / 0.01) / r1
+    w_out = 0.5 * math.tanh((r2 - 1.0) / 0.01) / r2
+    P = Problem("kelvin_helmholtz", nr, nth, r1, r2, tau, dt, steps, (WALL, WALL),
+                ((w_in, 0, 0, 0), (w_out, 0, 0, 0)), {"warmup": warmup})
+    R, TH = node_coords(nr, nth, r1, r2)
+    ut = 0.5 * np.tanh((R - 1.0) / 0.01)
+    ur = 1e-3 * np.sin(8.0 * TH) * np.exp(-((R - 1.0) / 0.02) ** 2)
+    return P, dict(rho=np.ones_like(R), ur=ur, ut=ut, T=np.ones_like(R))
+
+
+def uniform(nr, nth, r1=1.0, r2=2.0, rho=1.0, ux=0.0, uy=0.0, T=1.0, tau=1e-3,
+            bc=(WALL, WALL), bc_par=((0, 0, 0, 0), (0, 0, 0, 0)), cfl=0.3):
+    """A uniform state with Cartesian velocity (ux, uy), given in polar
+    components at each node."""
+    dt = cfl_dt(nr, nth, r1, r2, cfl)
+    P = Problem("uniform", nr, nth, r1, r2, tau, dt, 0, bc, bc_par)
+    R, TH = node_coords(nr, nth, r1, r2)
+    ur = ux * np.cos(TH) + uy * np.sin(TH)
+    ut = -ux * np.sin(TH) + uy * np.cos(TH)
+    return P, dict(rho=rho * np.ones_like(R), ur=ur, ut=ut, T=T * np.ones_like(R))
+
+
+def smooth_random(nr, nth, r1=1.0, r2=2.0, tau=2e-3, seed=0, amp=0.05, cfl=0.3,
+                  bc=(WALL, WALL), bc_par=((0.1, 0, 0, 0), (-0.05, 0, 0, 0))):
+    """Smooth seeded fields: a few low azimuthal/radial modes around rho = 1,
+    T = 1, u = 0, with relative amplitude ``amp``."""
+    rng = np.random.default_rng(seed)
+    dt = cfl_dt(nr, nth, r1, r2, cfl)
+    P = Problem("smooth_random", nr, nth, r1, r2, tau, dt, 0, bc, bc_par, {"seed": seed})
+    R, TH = node_coords(nr, nth, r1, r2)
+    x = (R - r1) / (r2 - r1)
+
+    def modes(scale):
+        out = np.zeros_like(R)
+        for m in range(1, 4):
+            for n in range(1, 3):
+                a, b, ph = rng.uniform(-1, 1, 3)
+                out += scale * a * np.cos(m * TH + math.pi * ph) * np.sin(math.pi * n * x + b)
+        return out
+
+    rho = 1.0 + modes(amp)
+    T = 1.0 + modes(amp)
+    ur = modes(amp)
+    ut = modes(amp)
+    return P, dict(rho=rho, ur=ur, ut=ut, T=T)
+
+
+def noise(shape, scale, seed) -> np.ndarray:
+    """Seeded uniform noise in [-scale, scale]."""
+    return scale * np.random.default_rng(seed).uniform(-1.0, 1.0, size=shape)
+
+
+def scaled(make, nr, nth, steps, **kw):
+    """The same recipe at another grid size (dt follows the CFL rule)."""
+    return make(nr=nr, nth=nth, steps=steps, **kw)
+
+
+#: The five measured configurations, by name.
+CONFIGS = {
+    "rotation_64x128": lambda: rotation(64, 128, 200),
+    "shock_tube_512x1024": lambda: shock_tube(512, 1024, 2000),
+    "richtmyer_meshkov_2048x4096": lambda: richtmyer_meshkov(2048, 4096, 5000),
+    "kelvin_helmholtz_4096x8192": lambda: kelvin_helmholtz(4096, 8192, 1000),
+    "adjoint_rm_1024x2048": lambda: richtmyer_meshkov(1024, 2048, 200),
+}
