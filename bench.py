@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the polar FDLB combined-scheme step on one MI355X.
+
+Workload (the headline configuration): Kelvin-Helmholtz shear layer on the
+annulus r in [0.5, 1.5] with 4096 x 8192 nodes and 33 velocities, FP32 state,
+CFL 0.3, tau = 1e-5; W warm-up steps, then K timed steps.  One step = one
+pass of the whole hot path (radial ghost layers, moments, equilibrium,
+relaxation, MWB convection in r and theta, store) over the whole grid.
+
+Printed: one JSON line with the metric (G cell-velocity updates per second),
+the roofline of the step kernel (algorithmic bytes / kernel time vs 8 TB/s),
+the CPU oracle timed on this host on a bounded sample, and extra figures: the
+FP64 step on the same grid and the adjoint/forward cost ratio on the
+1024 x 2048 Richtmyer-Meshkov adjoint configuration.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NQ = 33
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("common.h", "k_strip.hip", "k_forward.hip"):
+        with open(os.path.join(ROOT, "paper_1302_7104_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(precision: int, nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    entry = rec.get(f"fp{precision}")
+    if not entry or entry.get("nodes") != nodes:
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def time_steps(sim, torch, steps: int) -> float:
+    """Average ms per step over `steps` steps, HIP events on the sim's stream."""
+    st = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    sim.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_forward(W, Sim, torch, precision, steps, warmup, nr=4096, nth=8192):
+    P, F = W.kelvin_helmholtz(nr, nth, steps)
+    sim = Sim(P, precision=precision)
+    sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    del F
+    sim.step(warmup)
+    ms = time_steps(sim, torch, steps)
+    d = sim.diagnostics_host()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return P, ms, d
+
+
+def run_adjoint(W, torch, steps=200, ckpt=20, precision=32):
+    from paper_1302_7104_amd.sim import Evolve, InitState, Sim
+    P, F = W.richtmyer_meshkov(1024, 2048, steps)
+    sim = Sim(P, precision=precision)
+    dev = sim.device
+    amps = torch.as_tensor(W.rm_amplitudes(1), device=dev).requires_grad_(True)
+    _, Ft = W.richtmyer_meshkov(1024, 2048, steps, amps=amps, xp=torch)
+    f0 = InitState.apply(sim, Ft["rho"], Ft["ur"], Ft["ut"], Ft["T"])
+    torch.cuda.synchronize()
+    # forward alone (no checkpoints): the reference cost
+    sim.load_state(f0.detach())
+    ms_fwd = time_steps(sim, torch, steps)
+    R, _ = W.node_coords(P.nr, P.nth, P.r1, P.r2)
+    band = torch.as_tensor(((R > 1.1) & (R < 1.5)) * R * P.dr * P.dth, device=dev,
+                           dtype=torch.float32 if precision == 32 else torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn = Evolve.apply(sim, f0, steps, ckpt)
+    J = ((fn.sum(0) ** 2) * band).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grad = amps.grad.detach().cpu().numpy().tolist()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    ms_bwd_per_step = (t2 - t1) * 1e3 / steps
+    return dict(ms_forward_step=ms_fwd, ms_forward_with_checkpoints=(t1 - t0) * 1e3 / steps,
+                ms_backward_per_step=ms_bwd_per_step,
+                adjoint_over_forward=ms_bwd_per_step / ms_fwd, dJ_da=grad, J=float(J.item()))
+
+
+def cpu_baseline(W, target_s=12.0):
+    """The FP64 CPU oracle, as it stands, on the same recipe at 512 x 1024
+    (cost per cell-velocity update does not depend on the grid size)."""
+    from oracle import oracle as O
+    O.build(force=False)
+    P, F = W.kelvin_helmholtz(512, 1024, 1)
+    g = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par)
+    f = O.init_feq(g, **F)
+    t0 = time.perf_counter()
+    f, _ = O.step(g, f, 1)
+    one = time.perf_counter() - t0
+    n = max(1, int(target_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    f, _ = O.step(g, f, n)
+    dt = time.perf_counter() - t0
+    rate = NQ * P.nr * P.nth * n / dt / 1e9
+    return {"value": rate, "unit": "Gcell*vel/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"kelvin_helmholtz recipe at 512x1024 (33 velocities), {n} FP64 steps, "
+                      f"{dt:.1f} s on {O.num_threads()} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--no-extras", action="store_true", help="headline FP32 step only")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU execution "
+                          "(theta-sector sharding with halo exchange) is not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1302_7104_amd import workloads as W
+    from paper_1302_7104_amd.sim import Sim
+
+    P, ms, diag = run_forward(W, Sim, torch, 32, args.steps, args.warmup)
+    nodes = P.nr * P.nth
+    cellvel = NQ * nodes
+    value = cellvel / (ms * 1e-3) / 1e9
+    bytes_launch = 2 * NQ * nodes * 4
+    achieved = bytes_launch / (ms * 1e-3) / 1e9
+    traffic = stored_traffic(32, nodes)
+    out = {
+        "metric": "Gcell*vel updates/s (FP32 combined-scheme step)",
+        "value": value,
+        "unit": "Gcell*vel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "kelvin_helmholtz_4096x8192", "n_r": P.nr, "n_theta": P.nth,
+                   "velocities": NQ, "precision": "fp32 state, fp64 collision", "dt": P.dt,
+                   "tau": P.tau, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+    }
+    extra = {"mass_after_run": diag[0], "min_rho": diag[4], "min_T": diag[5]}
+    if not args.no_extras:
+        P64, ms64, _ = run_forward(W, Sim, torch, 64, args.fp64_steps, 10)
+        extra["fp64_ms_per_step"] = ms64
+        extra["fp64_gcellvel_per_s"] = cellvel / (ms64 * 1e-3) / 1e9
+        extra["fp64_hbm_frac"] = (2 * NQ * nodes * 8) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS
+        extra["adjoint_rm_1024x2048"] = run_adjoint(W, torch)
+    out["extra"] = extra
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * pclb.h — C ABI of the MI355X polar-coordinate FDLB library (libpclb.so).
+ *
+ * The library advances the 33 discrete-velocity distributions f_q of the
+ * octagon velocity model (Lin, Xu, Zhang, Li, Succi, "Polar coordinate lattice
+ * Boltzmann modeling of compressible flows", arXiv:1302.7104, Sec. II.A,
+ * Eq. DVM1 and Table I row 1) on an annulus R1 <= r <= R2 (Sec. II.C) with the
+ * combined scheme of Sec. II.B (Eq. combined_scheme): analytic BGK relaxation
+ * (Eq. operator1_new) plus the Modified Warming-Beam convection terms in r and
+ * theta (Eq. MWB Scheme with the switch S(eta) = (|eta|-1)/(|eta|+1)), all
+ * evaluated from f at time t.  Boundaries: periodic in theta over the full
+ * circle (Sec. II.C, azimuthal boundary condition with N_f = N_i), and two
+ * radial ghost layers per wall holding equilibria of linearly extrapolated
+ * density and temperature (Sec. II.C, radial boundary condition).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Distribution arrays are structure-of-arrays f[q][i][j] with q = 0..32
+ *    (q = 0 rest; q = 1 + 8(k-1) + d for speed group k = 1..4 and direction
+ *    d = 0..7 at angle d*pi/4), i = 0..n_r-1 radial (r_i = R1 + i*dr,
+ *    dr = (R2-R1)/(n_r-1)), j = 0..n_theta-1 azimuthal (theta_j =
+ *    (j+1)*2pi/n_theta), j fastest.  Element type: float when the context was
+ *    created with precision 32, double with precision 64.
+ *  - Field arrays (rho, u_r, u_theta, T and their cotangents) are double
+ *    [n_r][n_theta].  Velocities are polar components at each node.
+ *    T is the temperature, equal to the internal energy E since gamma = 2
+ *    (Sec. II.A).
+ *  - All pointers passed to entry points that launch kernels are DEVICE
+ *    pointers of the context's device and stay owned by the caller.  Work is
+ *    enqueued on the stream given to pclb_bind and is asynchronous unless the
+ *    entry point says it synchronizes.
+ *  - Every entry point returns PCLB_OK (0) or a negative PCLB_E* code; no C++
+ *    exception crosses the ABI.  pclb_last_error() describes the last failure.
+ */
+#ifndef PCLB_H
+#define PCLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pclb_ctx pclb_ctx;
+
+enum {
+  PCLB_OK = 0,
+  PCLB_EINVAL = -1,      /* bad argument or configuration */
+  PCLB_ECFL = -2,        /* a Courant number exceeds 1 (outside the monotone range) */
+  PCLB_EDEVICE = -3,     /* HIP runtime or launch failure */
+  PCLB_ENOMEM = -4,      /* device allocation failed */
+  PCLB_ESTATE = -5,      /* call not valid in the context's current state */
+  PCLB_ENONFINITE = -6   /* non-finite distribution found by a diagnostic */
+};
+
+/* Radial boundary kinds (Sec. II.C, radial boundary condition). */
+enum {
+  PCLB_WALL = 0,         /* p[0] = angular velocity omega: u = (0, omega r) at the ghosts */
+  PCLB_INFLOW = 1,       /* p = (rho, u_r, u_theta, T) prescribed at the ghosts */
+  PCLB_EXTRAPOLATE = 2   /* u_r, u_theta extrapolated linearly like rho and T */
+};
+
+/* Kernel selection for pclb_step / pclb_step_into. */
+enum {
+  PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
+  PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
+  PCLB_KERNEL_STRIP = 2    /* r-marching theta strips with a register ring */
+};
+
+typedef struct pclb_config {
+  int32_t n_r;           /* radial nodes, >= 4 */
+  int32_t n_theta;       /* azimuthal nodes, >= 8 */
+  double r1, r2;         /* annulus radii, 0 < r1 < r2 */
+  double tau;            /* relaxation time (Eq. FDLBM), > 0 */
+  double dt;             /* time step, > 0 */
+  int32_t n_i;           /* directions per speed group; must be 8 (octagon) */
+  int32_t n_f;           /* sector count N_f of Sec. II.C; must be 8 (full annulus) */
+  int32_t precision;     /* 32: float storage and convection, double collision;
+                            64: double throughout */
+  int32_t kernel;        /* PCLB_KERNEL_* */
+} pclb_config;
+
+/* Courant-number time step: dt = cfl * min(dr, r1*dtheta) / 4.49, 4.49 being
+ * the largest speed of the velocity set (Sec. II.A).  Returns a negative
+ * value if cfg describes no valid grid. */
+double pclb_cfl_dt(const pclb_config* cfg, double cfl);
+
+/* Validate cfg and create a context on the current HIP device.  Checks
+ * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i = n_f = 8,
+ * precision in {32, 64}, and max |C_r|, |C_theta| <= 1 (the monotone range of
+ * Sec. II.B, Eqs. varphi_0-varphi2e) -> PCLB_ECFL otherwise.  Allocates the
+ * context's small device tables and scratch (ghost layers, reduction
+ * partials).  *out is owned by the caller until pclb_destroy.  Both radial
+ * boundaries start as WALL with omega = 0. */
+int pclb_create(const pclb_config* cfg, pclb_ctx** out);
+
+/* Free the context's device tables and scratch.  NULL is accepted. */
+void pclb_destroy(pclb_ctx* ctx);
+
+/* Text of the last failure on ctx (or of the last failed pclb_create when ctx
+ * is NULL).  Static lifetime until the next call on the same context. */
+const char* pclb_last_error(const pclb_ctx* ctx);
+
+/* Bind two caller-owned device buffers of 33*n_r*n_theta elements each (the
+ * ping-pong pair) and the HIP stream (a hipStream_t, NULL = default stream)
+ * on which every later call enqueues its work.  Buffer 0 becomes current. */
+int pclb_bind(pclb_ctx* ctx, void* f0, void* f1, void* stream);
+
+/* Set the radial boundary of side 0 (inner, r = R1) or 1 (outer, r = R2).
+ * Host-side only; takes effect from the next launch. */
+int pclb_set_bc(pclb_ctx* ctx, int32_t side, int32_t kind, const double p[4]);
+
+/* f = f^eq(rho, u, T) on every node of the current buffer (Eq. feq with the
+ * weights of Eqs. F_k), from device field arrays; resets the step counter.
+ * Synchronizes the stream and returns PCLB_EINVAL if any rho <= 0, T <= 0 or
+ * non-finite input was found. */
+int pclb_init_state(pclb_ctx* ctx, const double* rho, const double* u_r,
+                    const double* u_theta, const double* T);
+
+/* Advance n >= 0 steps of Eq. combined_scheme on the bound buffers: per step
+ * one radial-ghost launch and one fused step launch, then the buffers swap.
+ * Asynchronous. */
+int pclb_step(pclb_ctx* ctx, int64_t n);
+
+/* One step from an arbitrary caller buffer f_in to f_out (both device
+ * buffers of the context's element type and size; they must not overlap).
+ * Used by checkpoint-recompute.  Does not touch the bound buffers or the step
+ * counter. */
+int pclb_step_into(pclb_ctx* ctx, const void* f_in, void* f_out);
+
+/* Which bound buffer (0 or 1) holds the current state. */
+int pclb_current(const pclb_ctx* ctx, int32_t* which);
+
+/* Number of steps taken since pclb_init_state (or since binding). */
+int pclb_step_count(const pclb_ctx* ctx, int64_t* steps);
+
+/* Macroscopic fields of the current state (Eqs. moment1-moment3): any of the
+ * four device field pointers may be NULL.  If diag8 (device, 8 doubles) is not
+ * NULL it receives {mass, P_x, P_y, total energy, min rho, min T,
+ * non-finite node count, step count}, the integrals taken with r dr dtheta,
+ * the trapezoidal rule in r and the rectangle rule in theta, accumulated in
+ * double with compensated (TwoSum) partial sums and a fixed-order second
+ * pass (bitwise reproducible).  Asynchronous. */
+int pclb_moments(pclb_ctx* ctx, double* rho, double* u_r, double* u_theta, double* T,
+                 double* diag8);
+
+/* Same diagnostics for an arbitrary state buffer f. */
+int pclb_moments_of(pclb_ctx* ctx, const void* f, double* rho, double* u_r, double* u_theta,
+                    double* T, double* diag8);
+
+/* Synchronizing variant: diagnostics of the current state copied to the host
+ * array diag8_host.  Returns PCLB_ENONFINITE if any node is non-finite. */
+int pclb_moments_host(pclb_ctx* ctx, double* diag8_host);
+
+/* One step of the discrete adjoint of Eq. combined_scheme (not in the paper):
+ * lam_out = (d Phi / d f at f_t)^T lam_next, where Phi is the step of
+ * pclb_step including the dependence of the radial ghost layers on the two
+ * real rows next to each wall.  The MWB switch is differentiated piecewise
+ * with sgn(0) = 0 and, where both upwind differences vanish, derivatives
+ * (1, 0) of (delta - delta')|delta|/(|delta|+|delta'|) with respect to
+ * (delta, delta').  All three buffers hold the context's element type and do
+ * not overlap.  Asynchronous. */
+int pclb_adjoint_step(pclb_ctx* ctx, const void* f_t, const void* lam_next, void* lam_out);
+
+/* Adjoint of pclb_init_state: from lam0 = dJ/df at f = f^eq(fields), write
+ * dJ/d(rho, u_r, u_theta, T) (device double fields; outputs overwritten). */
+int pclb_adjoint_init(pclb_ctx* ctx, const void* lam0, const double* rho, const double* u_r,
+                      const double* u_theta, const double* T, double* d_rho, double* d_u_r,
+                      double* d_u_theta, double* d_T);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCLB_H */

@@ -93,8 +93,10 @@ def lib():
         L.or_mwb_term.argtypes = [ctypes.c_double, _D, ctypes.c_int32]
         L.or_mwb_term.restype = ctypes.c_double
         L.or_mwb_grad.argtypes = [ctypes.c_double, _D, _D]
+        L.or_set_kink.argtypes = [ctypes.c_double, ctypes.c_double]
         L.or_step.argtypes = [G, _D, _D, ctypes.c_int32]
         L.or_step.restype = ctypes.c_int
+        L.or_step_sample.argtypes = [G, _D, _I, ctypes.c_int32, _D]
         L.or_init_feq.argtypes = [G, _D, _D, _D, _D, _D]
         L.or_fields.argtypes = [G, _D, _D, _D, _D, _D]
         L.or_diagnostics.argtypes = [G, _D, _D]
@@ -163,6 +165,11 @@ def mwb_grad(C, psi5) -> np.ndarray:
     return g
 
 
+def set_kink(h1: float, h2: float) -> None:
+    """(dh/d(delta), dh/d(delta')) used by the adjoint where delta = delta' = 0."""
+    lib().or_set_kink(float(h1), float(h2))
+
+
 def step(grid: Grid, f: np.ndarray, nsteps: int) -> tuple[np.ndarray, int]:
     """Eq. combined_scheme applied ``nsteps`` times.  Returns (f, bad_ghosts)."""
     f = _f64(f)
@@ -171,6 +178,18 @@ def step(grid: Grid, f: np.ndarray, nsteps: int) -> tuple[np.ndarray, int]:
     g = grid.c()
     bad = lib().or_step(ctypes.byref(g), _p(f), _p(out), int(nsteps))
     return out, bad
+
+
+def step_sample(grid: Grid, f: np.ndarray, nodes) -> np.ndarray:
+    """One step of Eq. combined_scheme at the listed (i, j) nodes only;
+    returns (len(nodes), 33).  ``f`` may be float32 or float64 (converted)."""
+    f = _f64(f)
+    assert f.shape == (NQ, grid.nr, grid.nth)
+    nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.int32).reshape(-1, 2))
+    out = np.empty((len(nd), NQ))
+    g = grid.c()
+    lib().or_step_sample(ctypes.byref(g), _p(f), nd.ctypes.data_as(_I), len(nd), _p(out))
+    return out
 
 
 def init_feq(grid: Grid, rho, ur, ut, T) -> np.ndarray:

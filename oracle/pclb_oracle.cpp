@@ -204,17 +204,21 @@ template <class T> T mwb_term(double C, const T psi[5], int s_mode) {
 // delta = 0 they come from forward-mode differentiation of the formula (with
 // sgn(0) = 0 inside |eta|).  At delta = 0 the term is C delta + C(1-|C|) h with
 // h = (delta - delta') |delta| / (|delta| + |delta'|): dh/d(delta) = 0 and
-// dh/d(delta') = 0 when delta' != 0, and (dh/d(delta), dh/d(delta')) = (1, 0)
-// when delta' = 0 as well.
+// dh/d(delta') = 0 when delta' != 0.  When delta' = 0 as well, h is not
+// differentiable; (dh/d(delta), dh/d(delta')) is then taken as KINK_H.
+double KINK_H[2] = {1.0, 0.0};
+
 void mwb_grad(double C, const double psi[5], double g[5]) {
   for (int n = 0; n < 5; ++n) g[n] = 0;
   double delta, dprime;
   if (C >= 0) { delta = psi[2] - psi[1]; dprime = psi[1] - psi[0]; }
   else        { delta = psi[3] - psi[2]; dprime = psi[4] - psi[3]; }
   if (delta == 0.0) {
-    double d_delta = C + C * (1.0 - std::fabs(C)) * (dprime == 0.0 ? 1.0 : 0.0);
-    if (C >= 0) { g[2] += d_delta; g[1] -= d_delta; }
-    else        { g[3] += d_delta; g[2] -= d_delta; }
+    double K = C * (1.0 - std::fabs(C));
+    double h1 = dprime == 0.0 ? KINK_H[0] : 0.0, h2 = dprime == 0.0 ? KINK_H[1] : 0.0;
+    double d_delta = C + K * h1, d_dprime = K * h2;
+    if (C >= 0) { g[2] += d_delta; g[1] -= d_delta; g[1] += d_dprime; g[0] -= d_dprime; }
+    else        { g[3] += d_delta; g[2] -= d_delta; g[4] += d_dprime; g[3] -= d_dprime; }
     return;
   }
   Dual<5> p[5];
@@ -411,6 +415,9 @@ double or_mwb_term(double C, const double* psi, int32_t s_mode) {
 
 void or_mwb_grad(double C, const double* psi, double* g) { mwb_grad(C, psi, g); }
 
+// Choice of (dh/d(delta), dh/d(delta')) where both upwind differences vanish.
+void or_set_kink(double h1, double h2) { KINK_H[0] = h1; KINK_H[1] = h2; }
+
 
 // Eq. combined_scheme applied nsteps times: f_out = f after nsteps steps.
 // f_in and f_out may alias.  Returns the number of ghost nodes that had a
@@ -457,6 +464,65 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
   }
   if (nsteps == 0) std::copy(cur.begin(), cur.end(), f_out);
   return bad;
+}
+
+// One step of Eq. combined_scheme evaluated only at the listed nodes
+// (nodes[2n] = i, nodes[2n+1] = j); out[n*33 + q] receives f_q at time t + dt.
+// Same arithmetic as or_step, restricted to the cross-shaped neighbourhood of
+// each node, so that very large grids can be sampled.
+void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int32_t count,
+                    double* out) {
+  const OrGrid& g = *gp;
+  Geometry geo(g);
+  double e = std::exp(-g.dt / g.tau);
+#pragma omp parallel for schedule(dynamic)
+  for (int n = 0; n < count; ++n) {
+    const int i = nodes[2 * n], j = nodes[2 * n + 1];
+    auto node_f = [&](int ii, int jj, double fl[NQ]) {
+      for (int q = 0; q < NQ; ++q) fl[q] = f[idx(g, q, ii, jj)];
+    };
+    // macroscopic fields of any real node
+    auto mac = [&](int ii, int jj, double m[4]) {
+      double fl[NQ];
+      node_f(ii, jj, fl);
+      macros(fl, m[0], m[1], m[2], m[3]);
+    };
+    // f_q at row ii (possibly a ghost row) and column jj (wrapped)
+    auto value = [&](int q, int ii, int jj) -> double {
+      jj = ((jj % g.nth) + g.nth) % g.nth;
+      if (ii >= 0 && ii < g.nr) return f[idx(g, q, ii, jj)];
+      int side = ii < 0 ? 0 : 1;
+      int i0 = side == 0 ? 0 : g.nr - 1, i1 = side == 0 ? 1 : g.nr - 2;
+      int ig1 = side == 0 ? -1 : g.nr, ig2 = side == 0 ? -2 : g.nr + 1;
+      double m0[4], m1[4], o1[4], o2[4];
+      mac(i0, jj, m0);
+      mac(i1, jj, m1);
+      ghost_macros<double>(g, side, geo.rr(ig1), geo.rr(ig2), geo.ct[jj], geo.st[jj], m0, m1, o1, o2);
+      const double* o = (ii == ig1) ? o1 : o2;
+      double F[NK + 1];
+      weights(o[3], TABLE1[0], F);
+      return feq_q(o[0], o[1], o[2], o[3], F, q);
+    };
+    double m[4];
+    mac(i, j, m);
+    double fe[NQ];
+    feq_all(m[0], m[1], m[2], m[3], fe);
+    double r = geo.rr(i);
+    for (int q = 0; q < NQ; ++q) {
+      double ft = f[idx(g, q, i, j)];
+      double res = fe[q] + (ft - fe[q]) * e;
+      double Cr = vr_of(q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
+      double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
+      double pr[5], pt[5];
+      for (int s = 0; s < 5; ++s) {
+        pr[s] = value(q, i - 2 + s, j);
+        pt[s] = value(q, i, j - 2 + s);
+      }
+      res -= mwb_term<double>(Cr, pr, 0);
+      res -= mwb_term<double>(Ct, pt, 0);
+      out[(size_t)n * NQ + q] = res;
+    }
+  }
 }
 
 // f = f^eq of given fields; u is given in polar components (u_r, u_theta) at

@@ -1,0 +1,349 @@
+// Forward kernels of the polar FDLB step: radial ghost layers, the per-node
+// reference step, initial equilibrium, macroscopic fields and diagnostics.
+// Sec. II of Lin et al. (arXiv:1302.7104).
+#include "common.h"
+#include "launch.h"
+
+namespace pclb {
+
+// ---------------------------------------------------------------------------
+// Radial ghost layers (Sec. II.C, radial boundary condition): from the two
+// real rows next to a wall take rho, u, E; extrapolate rho and E linearly and
+// recursively (ghost0 = 2 row0 - row1, ghost1 = 2 ghost0 - row0); set the
+// velocity per boundary kind; store f^eq of the ghost state.
+template <class R>
+__global__ void __launch_bounds__(256) ghost_kernel(Tables T, BCdev bc, const R* __restrict__ f,
+                                                    R* __restrict__ ghost) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int side = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  int i0 = side == 0 ? 0 : T.nr - 1;
+  int i1 = side == 0 ? 1 : T.nr - 2;
+  double m[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int i = s == 0 ? i0 : i1;
+    double fl[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fl[q] = (double)f[q * plane + (size_t)i * T.nth + j];
+    node_macros(fl, m[s][0], m[s][1], m[s][2], m[s][3]);
+  }
+  double ct = T.cth[j], st = T.sth[j];
+  double prev[4] = {m[0][0], m[0][1], m[0][2], m[0][3]};
+  double pprev[4] = {m[1][0], m[1][1], m[1][2], m[1][3]};
+  int kind = bc.kind[side];
+  for (int layer = 0; layer < 2; ++layer) {
+    double g[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) g[a] = 2.0 * prev[a] - pprev[a];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { pprev[a] = prev[a]; prev[a] = g[a]; }
+    double rho = g[0], ux = g[1], uy = g[2], E = g[3];
+    if (kind == 0) {                   // WALL: u_r = 0, u_theta = omega r_g
+      double ut = bc.p[side][0] * bc.rg[side][layer];
+      ux = -ut * st;
+      uy = ut * ct;
+    } else if (kind == 1) {            // INFLOW
+      rho = bc.p[side][0];
+      ux = bc.p[side][1] * ct - bc.p[side][2] * st;
+      uy = bc.p[side][1] * st + bc.p[side][2] * ct;
+      E = bc.p[side][3];
+    }                                  // EXTRAPOLATE keeps the extrapolated u
+    EqCoef c;
+    eq_setup(T, rho, ux, uy, E, c);
+    ghost[ghost_index(side, layer, 0, j, T.nth)] = (R)(c.rF[0] * c.A0);
+#pragma unroll
+    for (int k = 1; k <= NK; ++k)
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        ghost[ghost_index(side, layer, qidx(k, d), j, T.nth)] = (R)eq_val(c, k, d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reference step: one thread per node, neighbours read straight from global
+// memory (Eq. combined_scheme).  Used for small grids and as a cross-check of
+// the strip kernel.
+template <class R>
+__device__ inline R fetch(const R* __restrict__ f, const R* __restrict__ ghost, int q, int i, int j,
+                          int nr, int nth, size_t plane) {
+  if (i < 0) return ghost[ghost_index(0, -1 - i, q, j, nth)];
+  if (i >= nr) return ghost[ghost_index(1, i - nr, q, j, nth)];
+  return f[q * plane + (size_t)i * nth + j];
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) step_node_kernel(Tables T, const R* __restrict__ f,
+                                                        R* __restrict__ out,
+                                                        const R* __restrict__ ghost) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (j >= T.nth) return;
+  const int nr = T.nr, nth = T.nth;
+  const size_t plane = (size_t)nr * nth;
+  const size_t c0 = (size_t)i * nth + j;
+  R fc[NQ];
+  double fd[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) { fc[q] = f[q * plane + c0]; fd[q] = (double)fc[q]; }
+  double rho, ux, uy, E;
+  node_macros(fd, rho, ux, uy, E);
+  EqCoef ec;
+  eq_setup(T, rho, ux, uy, E, ec);
+  const double e = T.e;
+  {
+    double fe = ec.rF[0] * ec.A0;
+    out[c0] = (R)(fe + (fd[0] - fe) * e);     // rest velocity: no convection
+  }
+  const double ct = T.cth[j], st = T.sth[j];
+  const double sr = T.dt_dr, sth = T.dt_dth * T.rinv[i];
+  const int jm1 = j == 0 ? nth - 1 : j - 1, jm2 = jm1 == 0 ? nth - 1 : jm1 - 1;
+  const int jp1 = j == nth - 1 ? 0 : j + 1, jp2 = jp1 == nth - 1 ? 0 : jp1 + 1;
+#pragma unroll
+  for (int k = 1; k <= NK; ++k) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const int q = qidx(k, d);
+      double fe = eq_val(ec, k, d);
+      double relax = fe + (fd[q] - fe) * e;
+      double vr = vx_q(q) * ct + vy_q(q) * st;
+      double vt = -vx_q(q) * st + vy_q(q) * ct;
+      double Cr = vr * sr, Ct = vt * sth;
+      R u1, u2;
+      if (vr >= 0.0) {
+        u1 = fetch(f, ghost, q, i - 1, j, nr, nth, plane);
+        u2 = fetch(f, ghost, q, i - 2, j, nr, nth, plane);
+      } else {
+        u1 = fetch(f, ghost, q, i + 1, j, nr, nth, plane);
+        u2 = fetch(f, ghost, q, i + 2, j, nr, nth, plane);
+      }
+      double aC = fabs(Cr);
+      R Tr = mwb_term<R>((R)aC, (R)(aC * (1.0 - aC)), fc[q], u1, u2);
+      const R* pl = f + q * plane + (size_t)i * nth;
+      if (vt >= 0.0) { u1 = pl[jm1]; u2 = pl[jm2]; }
+      else           { u1 = pl[jp1]; u2 = pl[jp2]; }
+      aC = fabs(Ct);
+      R Tt = mwb_term<R>((R)aC, (R)(aC * (1.0 - aC)), fc[q], u1, u2);
+      out[q * plane + c0] = (R)relax - Tr - Tt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// f = f^eq(rho, u, T) with u given in polar components (Eq. feq).
+template <class R>
+__global__ void __launch_bounds__(256) init_kernel(Tables T, const double* __restrict__ rho,
+                                                   const double* __restrict__ ur,
+                                                   const double* __restrict__ ut,
+                                                   const double* __restrict__ Tt,
+                                                   R* __restrict__ f, int* __restrict__ bad) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  const size_t c0 = (size_t)i * T.nth + j;
+  double r = rho[c0], a = ur[c0], b = ut[c0], E = Tt[c0];
+  if (!(r > 0.0) || !(E > 0.0) || !isfinite(r) || !isfinite(E) || !isfinite(a) || !isfinite(b))
+    atomicOr(bad, 1);
+  double ct = T.cth[j], st = T.sth[j];
+  double ux = a * ct - b * st, uy = a * st + b * ct;
+  EqCoef c;
+  eq_setup(T, r, ux, uy, E, c);
+  f[c0] = (R)(c.rF[0] * c.A0);
+#pragma unroll
+  for (int k = 1; k <= NK; ++k)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) f[qidx(k, d) * plane + c0] = (R)eq_val(c, k, d);
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic fields (rho, u_r, u_theta, T) of every node; null outputs skipped.
+template <class R>
+__global__ void __launch_bounds__(256) fields_kernel(Tables T, const R* __restrict__ f,
+                                                     double* rho, double* ur, double* ut,
+                                                     double* Tt) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  const size_t c0 = (size_t)i * T.nth + j;
+  double fl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) fl[q] = (double)f[q * plane + c0];
+  double r, ux, uy, E;
+  node_macros(fl, r, ux, uy, E);
+  double ct = T.cth[j], st = T.sth[j];
+  if (rho) rho[c0] = r;
+  if (ur) ur[c0] = ux * ct + uy * st;
+  if (ut) ut[c0] = -ux * st + uy * ct;
+  if (Tt) Tt[c0] = E;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: compensated per-thread sums, a block tree of (sum, error)
+// pairs, and a one-block fixed-order final pass (deterministic).
+struct TwoS {
+  double s, c;
+};
+__device__ inline void two_add(TwoS& a, double x) {
+  double s = a.s + x;
+  double bb = s - a.s;
+  double err = (a.s - (s - bb)) + (x - bb);
+  a.s = s;
+  a.c += err;
+}
+__device__ inline TwoS two_merge(TwoS a, TwoS b) {
+  TwoS r = a;
+  two_add(r, b.s);
+  r.c += b.c;
+  return r;
+}
+
+constexpr int DIAG_BLOCK = 256;
+constexpr int DIAG_SLOTS = 11;   // 4 x (sum, err), min rho, min T, bad count
+
+template <class R>
+__global__ void __launch_bounds__(DIAG_BLOCK) diag_partial_kernel(Tables T, const R* __restrict__ f,
+                                                                  double* __restrict__ partial) {
+  const size_t plane = (size_t)T.nr * T.nth;
+  TwoS acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  double rmin = INFINITY, tmin = INFINITY, bad = 0.0;
+  for (size_t n = (size_t)blockIdx.x * DIAG_BLOCK + threadIdx.x; n < plane;
+       n += (size_t)gridDim.x * DIAG_BLOCK) {
+    int i = (int)(n / T.nth);
+    double fl[NQ];
+    bool fin = true;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      fl[q] = (double)f[q * plane + n];
+      fin = fin && isfinite(fl[q]);
+    }
+    if (!fin) { bad += 1.0; continue; }
+    double rho = 0, jx = 0, jy = 0, eps = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      rho += fl[q]; jx += fl[q] * vx_q(q); jy += fl[q] * vy_q(q); eps += fl[q] * v2_q(q);
+    }
+    eps *= 0.5;
+    double w = T.wA[i];
+    two_add(acc[0], rho * w);
+    two_add(acc[1], jx * w);
+    two_add(acc[2], jy * w);
+    two_add(acc[3], eps * w);
+    double ir = 1.0 / rho;
+    double ux = jx * ir, uy = jy * ir;
+    double E = eps * ir - 0.5 * (ux * ux + uy * uy);
+    rmin = fmin(rmin, rho);
+    tmin = fmin(tmin, E);
+  }
+  __shared__ double sh[DIAG_SLOTS][DIAG_BLOCK];
+  for (int a = 0; a < 4; ++a) { sh[2 * a][threadIdx.x] = acc[a].s; sh[2 * a + 1][threadIdx.x] = acc[a].c; }
+  sh[8][threadIdx.x] = rmin;
+  sh[9][threadIdx.x] = tmin;
+  sh[10][threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = DIAG_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      int o = threadIdx.x + w;
+      for (int a = 0; a < 4; ++a) {
+        TwoS x{sh[2 * a][threadIdx.x], sh[2 * a + 1][threadIdx.x]};
+        TwoS y{sh[2 * a][o], sh[2 * a + 1][o]};
+        TwoS z = two_merge(x, y);
+        sh[2 * a][threadIdx.x] = z.s;
+        sh[2 * a + 1][threadIdx.x] = z.c;
+      }
+      sh[8][threadIdx.x] = fmin(sh[8][threadIdx.x], sh[8][o]);
+      sh[9][threadIdx.x] = fmin(sh[9][threadIdx.x], sh[9][o]);
+      sh[10][threadIdx.x] += sh[10][o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < DIAG_SLOTS) partial[(size_t)blockIdx.x * DIAG_SLOTS + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(64) diag_final_kernel(const double* __restrict__ partial, int nb,
+                                                        double step, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  TwoS acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  double rmin = INFINITY, tmin = INFINITY, bad = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double* p = partial + (size_t)b * DIAG_SLOTS;
+    for (int a = 0; a < 4; ++a) acc[a] = two_merge(acc[a], TwoS{p[2 * a], p[2 * a + 1]});
+    rmin = fmin(rmin, p[8]);
+    tmin = fmin(tmin, p[9]);
+    bad += p[10];
+  }
+  for (int a = 0; a < 4; ++a) out[a] = acc[a].s + acc[a].c;
+  out[4] = rmin;
+  out[5] = tmin;
+  out[6] = bad;
+  out[7] = step;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side).
+template <class R>
+hipError_t launch_ghost(const Tables& T, const BCdev& bc, const void* f, void* ghost, hipStream_t s) {
+  dim3 grid((T.nth + 255) / 256, 2);
+  hipLaunchKernelGGL(ghost_kernel<R>, grid, dim3(256), 0, s, T, bc, (const R*)f, (R*)ghost);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_step_node(const Tables& T, const void* f, void* out, const void* ghost, hipStream_t s) {
+  dim3 grid((T.nth + 255) / 256, T.nr);
+  hipLaunchKernelGGL(step_node_kernel<R>, grid, dim3(256), 0, s, T, (const R*)f, (R*)out, (const R*)ghost);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_init(const Tables& T, const double* rho, const double* ur, const double* ut,
+                       const double* Tt, void* f, int* bad, hipStream_t s) {
+  dim3 grid((T.nth + 255) / 256, T.nr);
+  hipLaunchKernelGGL(init_kernel<R>, grid, dim3(256), 0, s, T, rho, ur, ut, Tt, (R*)f, bad);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_fields(const Tables& T, const void* f, double* rho, double* ur, double* ut,
+                         double* Tt, hipStream_t s) {
+  dim3 grid((T.nth + 255) / 256, T.nr);
+  hipLaunchKernelGGL(fields_kernel<R>, grid, dim3(256), 0, s, T, (const R*)f, rho, ur, ut, Tt);
+  return hipGetLastError();
+}
+
+__global__ void zero_int_kernel(int* p) { if (threadIdx.x == 0) *p = 0; }
+
+hipError_t launch_zero_int(int* p, hipStream_t s) {
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, p);
+  return hipGetLastError();
+}
+
+int diag_blocks() { return 1024; }
+int diag_slots() { return DIAG_SLOTS; }
+
+template <class R>
+hipError_t launch_diag(const Tables& T, const void* f, double* partial, double step, double* out,
+                       hipStream_t s) {
+  int nb = diag_blocks();
+  hipLaunchKernelGGL(diag_partial_kernel<R>, dim3(nb), dim3(DIAG_BLOCK), 0, s, T, (const R*)f, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partial, nb, step, out);
+  return hipGetLastError();
+}
+
+#define PCLB_INST(R)                                                                              \
+  template hipError_t launch_ghost<R>(const Tables&, const BCdev&, const void*, void*, hipStream_t); \
+  template hipError_t launch_step_node<R>(const Tables&, const void*, void*, const void*, hipStream_t); \
+  template hipError_t launch_init<R>(const Tables&, const double*, const double*, const double*,  \
+                                     const double*, void*, int*, hipStream_t);                    \
+  template hipError_t launch_fields<R>(const Tables&, const void*, double*, double*, double*,     \
+                                       double*, hipStream_t);                                     \
+  template hipError_t launch_diag<R>(const Tables&, const void*, double*, double, double*, hipStream_t);
+PCLB_INST(float)
+PCLB_INST(double)
+#undef PCLB_INST
+
+}  // namespace pclb

@@ -1,0 +1,42 @@
+// Host-side launchers of the kernels (one per kernel family, templated on the
+// storage type: float for precision 32, double for precision 64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace pclb {
+
+template <class R>
+hipError_t launch_ghost(const Tables& T, const BCdev& bc, const void* f, void* ghost, hipStream_t s);
+template <class R>
+hipError_t launch_step_node(const Tables& T, const void* f, void* out, const void* ghost, hipStream_t s);
+template <class R>
+hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
+                             int chunk_rows, hipStream_t s);
+template <class R>
+bool strip_supported(const Tables& T);
+template <class R>
+hipError_t launch_init(const Tables& T, const double* rho, const double* ur, const double* ut,
+                       const double* Tt, void* f, int* bad, hipStream_t s);
+template <class R>
+hipError_t launch_fields(const Tables& T, const void* f, double* rho, double* ur, double* ut,
+                         double* Tt, hipStream_t s);
+template <class R>
+hipError_t launch_diag(const Tables& T, const void* f, double* partial, double step, double* out,
+                       hipStream_t s);
+hipError_t launch_zero_int(int* p, hipStream_t s);
+int diag_blocks();
+int diag_slots();
+
+// Adjoint.
+template <class R>
+hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const void* lam,
+                          void* lam_out, void* ghost, void* gadj, double* gm, hipStream_t s);
+template <class R>
+hipError_t launch_adjoint_init(const Tables& T, const void* lam, const double* rho,
+                               const double* ur, const double* ut, const double* Tt, double* d_rho,
+                               double* d_ur, double* d_ut, double* d_T, hipStream_t s);
+
+}  // namespace pclb

@@ -1,0 +1,353 @@
+// C ABI of libpclb.so: context, validation, geometry and weight tables, and
+// launch orchestration of the polar FDLB step (see include/pclb.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/pclb.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace pclb;
+
+struct pclb_ctx {
+  pclb_config cfg{};
+  int device = 0;
+  double dr = 0, dth = 0;
+  Tables T{};
+  BCdev bc{};
+  void* f[2] = {nullptr, nullptr};
+  int cur = 0;
+  bool bound = false;
+  hipStream_t stream = nullptr;
+  int64_t steps = 0;
+  // context-owned device memory
+  double* d_geom = nullptr;     // cth[nth], sth[nth], rinv[nr], wA[nr]
+  void* d_ghost = nullptr;      // 4 * 33 * nth elements of the state type
+  double* d_partial = nullptr;  // diagnostics partials
+  double* d_diag = nullptr;     // 8 doubles for the synchronizing variant
+  int* d_flag = nullptr;        // init validation flag
+  double* d_gm = nullptr;       // adjoint: ghost moment cotangents 2*2*4*nth
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double PI = 3.14159265358979323846;
+
+size_t elem_size(const pclb_ctx* c) { return c->cfg.precision == 32 ? 4 : 8; }
+
+int fail(pclb_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+int hip_fail(pclb_ctx* c, hipError_t e, const char* where) {
+  return fail(c, PCLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Horner coefficients of F_k(E) for the octagon model: Eqs. F_k with the
+// first row of Table I, B = (B0, B1, B2, B3, B4) = (8, -1/4, 1, -6, 48),
+// suffixes {k+l} = mod{k+l, 4}.  F_k(E) = E (c0 + E (c1 + E (c2 + E c3))) with
+// c0 = B1 e3 / den, c1 = B2 e2 / den, c2 = B3 e1 / den, c3 = B4 / den, where
+// e1, e2, e3 are the elementary symmetric sums of the other three v^2 and
+// den = v_k^2 prod_l (v_k^2 - v_l^2).
+void weight_coefficients(double fc[NK][4]) {
+  const double B1 = -0.25, B2 = 1.0, B3 = -6.0, B4 = 48.0;
+  double x[NK + 1];
+  for (int k = 0; k <= NK; ++k) x[k] = speed(k) * speed(k);
+  for (int k = 1; k <= NK; ++k) {
+    int o[3];
+    for (int l = 1; l <= 3; ++l) o[l - 1] = (k + l <= NK) ? k + l : k + l - NK;
+    double a = x[o[0]], b = x[o[1]], c = x[o[2]];
+    double den = x[k] * (x[k] - a) * (x[k] - b) * (x[k] - c);
+    fc[k - 1][0] = B1 * a * b * c / den;
+    fc[k - 1][1] = B2 * (a * b + b * c + c * a) / den;
+    fc[k - 1][2] = B3 * (a + b + c) / den;
+    fc[k - 1][3] = B4 / den;
+  }
+}
+
+int validate(const pclb_config* c, std::string& why) {
+  if (!c) { why = "null config"; return PCLB_EINVAL; }
+  if (!(c->r1 > 0.0) || !(c->r2 > c->r1)) { why = "need 0 < r1 < r2"; return PCLB_EINVAL; }
+  if (c->n_r < 4) { why = "n_r must be >= 4"; return PCLB_EINVAL; }
+  if (c->n_theta < 8) { why = "n_theta must be >= 8"; return PCLB_EINVAL; }
+  if ((int64_t)c->n_r * c->n_theta > (int64_t)1 << 31) { why = "grid too large"; return PCLB_EINVAL; }
+  if (!(c->tau > 0.0) || !std::isfinite(c->tau)) { why = "tau must be > 0"; return PCLB_EINVAL; }
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) { why = "dt must be > 0"; return PCLB_EINVAL; }
+  if (c->n_i != 8) { why = "only the octagon model (n_i = 8) is built"; return PCLB_EINVAL; }
+  if (c->n_f != 8) { why = "only the full annulus (n_f = n_i = 8) is built"; return PCLB_EINVAL; }
+  if (c->precision != 32 && c->precision != 64) { why = "precision must be 32 or 64"; return PCLB_EINVAL; }
+  if (c->kernel < 0 || c->kernel > 2) { why = "unknown kernel selection"; return PCLB_EINVAL; }
+  double dr = (c->r2 - c->r1) / (c->n_r - 1);
+  double dth = 2.0 * PI / c->n_theta;
+  double vmax = speed(NK);
+  double cr = vmax * c->dt / dr, ct = vmax * c->dt / (c->r1 * dth);
+  if (cr > 1.0 || ct > 1.0) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "Courant numbers max|C_r| = %.4g, max|C_theta| = %.4g exceed 1", cr, ct);
+    why = buf;
+    return PCLB_ECFL;
+  }
+  return PCLB_OK;
+}
+
+template <class R>
+hipError_t do_step(pclb_ctx* c, const void* in, void* out) {
+  hipError_t e = launch_ghost<R>(c->T, c->bc, in, c->d_ghost, c->stream);
+  if (e != hipSuccess) return e;
+  int kern = c->cfg.kernel;
+  if (kern == PCLB_KERNEL_STRIP || (kern == PCLB_KERNEL_AUTO && strip_supported<R>(c->T)))
+    if (strip_supported<R>(c->T)) return launch_step_strip<R>(c->T, in, out, c->d_ghost, 0, c->stream);
+  return launch_step_node<R>(c->T, in, out, c->d_ghost, c->stream);
+}
+
+hipError_t step_once(pclb_ctx* c, const void* in, void* out) {
+  return c->cfg.precision == 32 ? do_step<float>(c, in, out) : do_step<double>(c, in, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+double pclb_cfl_dt(const pclb_config* cfg, double cfl) {
+  if (!cfg || !(cfg->r1 > 0) || !(cfg->r2 > cfg->r1) || cfg->n_r < 2 || cfg->n_theta < 1 || !(cfl > 0))
+    return -1.0;
+  double dr = (cfg->r2 - cfg->r1) / (cfg->n_r - 1);
+  double dth = 2.0 * PI / cfg->n_theta;
+  return cfl * std::fmin(dr, cfg->r1 * dth) / speed(NK);
+}
+
+int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
+  if (!out) return fail(nullptr, PCLB_EINVAL, "null output pointer");
+  *out = nullptr;
+  std::string why;
+  int rc = validate(cfg, why);
+  if (rc != PCLB_OK) return fail(nullptr, rc, why);
+  pclb_ctx* c = new (std::nothrow) pclb_ctx();
+  if (!c) return fail(nullptr, PCLB_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { delete c; return fail(nullptr, PCLB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
+  const int nr = cfg->n_r, nth = cfg->n_theta;
+  c->dr = (cfg->r2 - cfg->r1) / (nr - 1);
+  c->dth = 2.0 * PI / nth;
+  // geometry tables: node angles theta_j = (j+1) dtheta, radii r_i = R1 + i dr
+  std::string host_err;
+  size_t ngeom = 2 * (size_t)nth + 2 * (size_t)nr;
+  double* h = new (std::nothrow) double[ngeom];
+  if (!h) { delete c; return fail(nullptr, PCLB_ENOMEM, "host allocation failed"); }
+  for (int j = 0; j < nth; ++j) {
+    double th = (j + 1) * c->dth;
+    h[j] = std::cos(th);
+    h[nth + j] = std::sin(th);
+  }
+  for (int i = 0; i < nr; ++i) {
+    double r = cfg->r1 + i * c->dr;
+    h[2 * nth + i] = 1.0 / r;
+    double w = (i == 0 || i == nr - 1) ? 0.5 : 1.0;
+    h[2 * nth + nr + i] = r * w * c->dr * c->dth;
+  }
+  size_t es = cfg->precision == 32 ? 4 : 8;
+  bool ok = hipMalloc(&c->d_geom, ngeom * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_ghost, 4 * (size_t)NQ * nth * es) == hipSuccess &&
+            hipMalloc(&c->d_partial, (size_t)diag_blocks() * diag_slots() * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_diag, 8 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_flag, sizeof(int)) == hipSuccess &&
+            hipMalloc(&c->d_gm, 16 * (size_t)nth * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    delete[] h;
+    pclb_destroy(c);
+    return fail(nullptr, PCLB_ENOMEM, "device allocation of context tables failed");
+  }
+  e = hipMemcpy(c->d_geom, h, ngeom * sizeof(double), hipMemcpyHostToDevice);
+  delete[] h;
+  if (e != hipSuccess) { pclb_destroy(c); return fail(nullptr, PCLB_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e)); }
+  Tables& T = c->T;
+  T.nr = nr;
+  T.nth = nth;
+  T.dt_dr = cfg->dt / c->dr;
+  T.dt_dth = cfg->dt / c->dth;
+  T.e = std::exp(-cfg->dt / cfg->tau);
+  weight_coefficients(T.fc);
+  T.cth = c->d_geom;
+  T.sth = c->d_geom + nth;
+  T.rinv = c->d_geom + 2 * nth;
+  T.wA = c->d_geom + 2 * nth + nr;
+  for (int s = 0; s < 2; ++s) {
+    c->bc.kind[s] = PCLB_WALL;
+    for (int a = 0; a < 4; ++a) c->bc.p[s][a] = 0.0;
+  }
+  c->bc.rg[0][0] = cfg->r1 - c->dr;
+  c->bc.rg[0][1] = cfg->r1 - 2.0 * c->dr;
+  c->bc.rg[1][0] = cfg->r2 + c->dr;
+  c->bc.rg[1][1] = cfg->r2 + 2.0 * c->dr;
+  *out = c;
+  return PCLB_OK;
+}
+
+void pclb_destroy(pclb_ctx* c) {
+  if (!c) return;
+  if (c->d_geom) (void)hipFree(c->d_geom);
+  if (c->d_ghost) (void)hipFree(c->d_ghost);
+  if (c->d_partial) (void)hipFree(c->d_partial);
+  if (c->d_diag) (void)hipFree(c->d_diag);
+  if (c->d_flag) (void)hipFree(c->d_flag);
+  if (c->d_gm) (void)hipFree(c->d_gm);
+  delete c;
+}
+
+const char* pclb_last_error(const pclb_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int pclb_bind(pclb_ctx* c, void* f0, void* f1, void* stream) {
+  if (!c) return PCLB_EINVAL;
+  if (!f0 || !f1 || f0 == f1) return fail(c, PCLB_EINVAL, "two distinct non-null buffers are required");
+  c->f[0] = f0;
+  c->f[1] = f1;
+  c->cur = 0;
+  c->stream = (hipStream_t)stream;
+  c->bound = true;
+  c->steps = 0;
+  return PCLB_OK;
+}
+
+int pclb_set_bc(pclb_ctx* c, int32_t side, int32_t kind, const double p[4]) {
+  if (!c) return PCLB_EINVAL;
+  if (side < 0 || side > 1) return fail(c, PCLB_EINVAL, "side must be 0 (inner) or 1 (outer)");
+  if (kind < PCLB_WALL || kind > PCLB_EXTRAPOLATE) return fail(c, PCLB_EINVAL, "unknown boundary kind");
+  double q[4] = {0, 0, 0, 0};
+  if (kind != PCLB_EXTRAPOLATE) {
+    if (!p) return fail(c, PCLB_EINVAL, "boundary parameters required");
+    for (int a = 0; a < 4; ++a) q[a] = p[a];
+  }
+  for (int a = 0; a < 4; ++a)
+    if (!std::isfinite(q[a])) return fail(c, PCLB_EINVAL, "non-finite boundary parameter");
+  if (kind == PCLB_INFLOW && (!(q[0] > 0.0) || !(q[3] > 0.0)))
+    return fail(c, PCLB_EINVAL, "inflow density and temperature must be > 0");
+  c->bc.kind[side] = kind;
+  for (int a = 0; a < 4; ++a) c->bc.p[side][a] = q[a];
+  return PCLB_OK;
+}
+
+int pclb_init_state(pclb_ctx* c, const double* rho, const double* ur, const double* ut, const double* T) {
+  if (!c) return PCLB_EINVAL;
+  if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
+  if (!rho || !ur || !ut || !T) return fail(c, PCLB_EINVAL, "null field pointer");
+  hipError_t e = launch_zero_int(c->d_flag, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "flag reset");
+  e = c->cfg.precision == 32
+          ? launch_init<float>(c->T, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream)
+          : launch_init<double>(c->T, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "init launch");
+  int flag = 0;
+  e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "init sync");
+  c->steps = 0;
+  if (flag) return fail(c, PCLB_EINVAL, "initial fields need rho > 0, T > 0 and finite values");
+  return PCLB_OK;
+}
+
+int pclb_step(pclb_ctx* c, int64_t n) {
+  if (!c) return PCLB_EINVAL;
+  if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
+  if (n < 0) return fail(c, PCLB_EINVAL, "negative step count");
+  for (int64_t s = 0; s < n; ++s) {
+    hipError_t e = step_once(c, c->f[c->cur], c->f[1 - c->cur]);
+    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    c->cur = 1 - c->cur;
+    ++c->steps;
+  }
+  return PCLB_OK;
+}
+
+int pclb_step_into(pclb_ctx* c, const void* f_in, void* f_out) {
+  if (!c) return PCLB_EINVAL;
+  if (!f_in || !f_out || f_in == f_out) return fail(c, PCLB_EINVAL, "distinct non-null buffers required");
+  hipError_t e = step_once(c, f_in, f_out);
+  if (e != hipSuccess) return hip_fail(c, e, "step launch");
+  return PCLB_OK;
+}
+
+int pclb_current(const pclb_ctx* c, int32_t* which) {
+  if (!c || !which) return PCLB_EINVAL;
+  *which = c->cur;
+  return PCLB_OK;
+}
+
+int pclb_step_count(const pclb_ctx* c, int64_t* steps) {
+  if (!c || !steps) return PCLB_EINVAL;
+  *steps = c->steps;
+  return PCLB_OK;
+}
+
+int pclb_moments_of(pclb_ctx* c, const void* f, double* rho, double* ur, double* ut, double* T,
+                    double* diag8) {
+  if (!c) return PCLB_EINVAL;
+  if (!f) return fail(c, PCLB_EINVAL, "null state buffer");
+  hipError_t e = hipSuccess;
+  if (rho || ur || ut || T)
+    e = c->cfg.precision == 32 ? launch_fields<float>(c->T, f, rho, ur, ut, T, c->stream)
+                               : launch_fields<double>(c->T, f, rho, ur, ut, T, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "fields launch");
+  if (diag8) {
+    e = c->cfg.precision == 32 ? launch_diag<float>(c->T, f, c->d_partial, (double)c->steps, diag8, c->stream)
+                               : launch_diag<double>(c->T, f, c->d_partial, (double)c->steps, diag8, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
+  }
+  return PCLB_OK;
+}
+
+int pclb_moments(pclb_ctx* c, double* rho, double* ur, double* ut, double* T, double* diag8) {
+  if (!c) return PCLB_EINVAL;
+  if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
+  return pclb_moments_of(c, c->f[c->cur], rho, ur, ut, T, diag8);
+}
+
+int pclb_moments_host(pclb_ctx* c, double* diag8_host) {
+  if (!c) return PCLB_EINVAL;
+  if (!diag8_host) return fail(c, PCLB_EINVAL, "null output");
+  int rc = pclb_moments(c, nullptr, nullptr, nullptr, nullptr, c->d_diag);
+  if (rc != PCLB_OK) return rc;
+  hipError_t e = hipMemcpyAsync(diag8_host, c->d_diag, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics copy");
+  if (diag8_host[6] != 0.0) return fail(c, PCLB_ENONFINITE, "non-finite distribution values found");
+  return PCLB_OK;
+}
+
+int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* lam_out) {
+  if (!c) return PCLB_EINVAL;
+  if (!f_t || !lam_next || !lam_out || lam_out == lam_next || lam_out == f_t)
+    return fail(c, PCLB_EINVAL, "three non-null buffers, lam_out distinct from the inputs");
+  hipError_t e = c->cfg.precision == 32
+                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, nullptr, c->d_gm, c->stream)
+                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, nullptr, c->d_gm, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+  return PCLB_OK;
+}
+
+int pclb_adjoint_init(pclb_ctx* c, const void* lam0, const double* rho, const double* ur,
+                      const double* ut, const double* T, double* d_rho, double* d_ur, double* d_ut,
+                      double* d_T) {
+  if (!c) return PCLB_EINVAL;
+  if (!lam0 || !rho || !ur || !ut || !T || !d_rho || !d_ur || !d_ut || !d_T)
+    return fail(c, PCLB_EINVAL, "null pointer");
+  hipError_t e = c->cfg.precision == 32
+                     ? launch_adjoint_init<float>(c->T, lam0, rho, ur, ut, T, d_rho, d_ur, d_ut, d_T, c->stream)
+                     : launch_adjoint_init<double>(c->T, lam0, rho, ur, ut, T, d_rho, d_ur, d_ut, d_T, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint init launch");
+  return PCLB_OK;
+}
+
+}  // extern "C"

@@ -28,6 +28,9 @@ import numpy as np
 # Radial boundary kinds (Sec. II.C, radial boundary condition).
 WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
 
+#: Courant number of the time-step rule used by every recipe (see cfl_dt).
+CFL = 0.2
+
 #: largest speed of the discrete velocity set (v_4 of Sec. II.A); used only by
 #: the time-step rule below.
 MAX_SPEED = 4.49
@@ -94,9 +97,9 @@ def hugoniot(rho0: float, u0: float, P0: float, D: float, gamma: float = 2.0):
 # Problem definitions.  Each returns (Problem, fields) where fields is a dict of
 # float64 arrays rho, ur, ut, T of shape (nr, nth).
 
-def rotation(nr=64, nth=128, steps=200, hydrostatic=False, omega=0.5, tau=1e-4):
+def rotation(nr=64, nth=128, steps=200, hydrostatic=False, omega=0.5, tau=1e-4, cfl=None):
     r1, r2 = 1.0, 2.0
-    dt = cfl_dt(nr, nth, r1, r2)
+    dt = cfl_dt(nr, nth, r1, r2, CFL if cfl is None else cfl)
     P = Problem("rotation_hydrostatic" if hydrostatic else "rotation", nr, nth, r1, r2, tau, dt,
                 steps, (WALL, WALL), ((omega, 0, 0, 0), (omega, 0, 0, 0)),
                 {"omega": omega})
@@ -106,9 +109,9 @@ def rotation(nr=64, nth=128, steps=200, hydrostatic=False, omega=0.5, tau=1e-4):
     return P, dict(rho=rho, ur=np.zeros_like(R), ut=omega * R, T=T)
 
 
-def shock_tube(nr=512, nth=1024, steps=2000, tau=2e-5, noise=1e-6, seed=0):
+def shock_tube(nr=512, nth=1024, steps=2000, tau=2e-5, noise=1e-6, seed=0, cfl=None):
     r1, r2 = 0.2, 1.2
-    dt = cfl_dt(nr, nth, r1, r2)
+    dt = cfl_dt(nr, nth, r1, r2, CFL if cfl is None else cfl)
     P = Problem("shock_tube", nr, nth, r1, r2, tau, dt, steps, (WALL, WALL),
                 ((0, 0, 0, 0), (0, 0, 0, 0)), {"seed": seed, "noise": noise})
     R, TH = node_coords(nr, nth, r1, r2)
@@ -129,7 +132,7 @@ def rm_amplitudes(seed=1) -> np.ndarray:
 
 
 def richtmyer_meshkov(nr=2048, nth=4096, steps=5000, tau=2e-5, amps=None, seed=1,
-                      width=0.005, pressure_balance=False, xp=np):
+                      width=0.005, pressure_balance=False, xp=np, cfl=None):
     """Shock of Mach 2 (gamma = 2) at r = 0.8 moving outward into rho = 1,
     T = 1; interface r_I = 1.2 + sum_k a_k cos(k theta) between rho = 1 and
     rho = 3, smoothed as a tanh of width ``width``.  With pressure_balance the
@@ -137,7 +140,7 @@ def richtmyer_meshkov(nr=2048, nth=4096, steps=5000, tau=2e-5, amps=None, seed=1
     otherwise T = 1 on both sides.  ``amps`` may be a torch tensor (then
     xp=torch) so that the fields are differentiable in a_k."""
     r1, r2 = 0.2, 2.2
-    dt = cfl_dt(nr, nth, r1, r2)
+    dt = cfl_dt(nr, nth, r1, r2, CFL if cfl is None else cfl)
     c0 = math.sqrt(2.0)
     D = 2.0 * c0
     rhoH, uH, PH = hugoniot(1.0, 0.0, 1.0, D)
@@ -179,11 +182,14 @@ def rm_interface_sensitivity(P: Problem, amps) -> np.ndarray:
     return out
 
 
-def kelvin_helmholtz(nr=4096, nth=8192, steps=1000, tau=1e-5, warmup=50):
+def kelvin_helmholtz(nr=4096, nth=8192, steps=1000, tau=1e-5, warmup=50, cfl=None,
+                     tau_equals_dt=False):
     """u_theta = 0.5 tanh((r-1)/0.01), u_r = 1e-3 sin(8 theta) exp(-((r-1)/0.02)^2),
     rho = 1, T = 1 on r in [0.5, 1.5]; walls turning with the flow at r = 0.5, 1.5."""
     r1, r2 = 0.5, 1.5
-    dt = cfl_dt(nr, nth, r1, r2)
+    dt = cfl_dt(nr, nth, r1, r2, CFL if cfl is None else cfl)
+    if tau_equals_dt:
+        tau = dt
     w_in = 0.5 * math.tanh((r1 - 1.0) / 0.01) / r1
     w_out = 0.5 * math.tanh((r2 - 1.0) / 0.01) / r2
     P = Problem("kelvin_helmholtz", nr, nth, r1, r2, tau, dt, steps, (WALL, WALL),
@@ -249,3 +255,13 @@ CONFIGS = {
     "kelvin_helmholtz_4096x8192": lambda: kelvin_helmholtz(4096, 8192, 1000),
     "adjoint_rm_1024x2048": lambda: richtmyer_meshkov(1024, 2048, 200),
 }
+
+
+def reduced(make, nr, nth, steps, full=(None, None), **kw):
+    """The recipe ``make`` on a smaller nr x nth grid with tau rescaled so that
+    dt/tau (and the Courant numbers, which the time-step rule fixes) equal
+    those of the recipe at the full size ``full`` = (nr, nth)."""
+    P_full, _ = make(nr=full[0], nth=full[1], steps=1, **kw)
+    P, F = make(nr=nr, nth=nth, steps=steps, **kw)
+    tau = P.dt / (P_full.dt / P_full.tau)
+    return replace(P, tau=tau), F

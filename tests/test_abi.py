@@ -1,0 +1,57 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/pclb.h declares, and rejects invalid configurations before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1302_7104_amd import _native as N
+from paper_1302_7104_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pclb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pclb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(N.SYMBOLS) == declared_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def cfg(**kw):
+    base = dict(n_r=64, n_theta=128, r1=1.0, r2=2.0, tau=1e-4, dt=1e-3, n_i=8, n_f=8,
+                precision=64, kernel=0)
+    base.update(kw)
+    return N.Config(*[base[k] for k, _ in N.Config._fields_])
+
+
+def test_cfl_dt_matches_workload_rule():
+    c = cfg()
+    dt = N.lib().pclb_cfl_dt(ctypes.byref(c), 0.3)
+    assert abs(dt - W.cfl_dt(64, 128, 1.0, 2.0, 0.3)) < 1e-18
+    assert N.lib().pclb_cfl_dt(ctypes.byref(cfg(r1=-1.0)), 0.3) < 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(r1=0.0), -1), (dict(r2=0.5), -1), (dict(n_r=3), -1), (dict(n_theta=4), -1),
+    (dict(tau=0.0), -1), (dict(dt=-1.0), -1), (dict(n_i=16), -1), (dict(n_f=1), -1),
+    (dict(precision=16), -1), (dict(kernel=7), -1), (dict(dt=0.01), -2),
+])
+def test_create_rejects_invalid_config(kw, code):
+    L = N.lib()
+    ctx = ctypes.c_void_p()
+    rc = L.pclb_create(ctypes.byref(cfg(**kw)), ctypes.byref(ctx))
+    assert rc == code
+    assert not ctx.value
+    assert L.pclb_last_error(None)

@@ -1,0 +1,394 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Both sides receive the same seeded inputs from ``workloads``; the oracle
+computes its own initial state.  Bars: FP64 normwise relative error
+<= 1e-12; FP32 within the tolerances stated per test (FP32 storage and
+convection, double collision).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1302_7104_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1302_7104_amd import _native
+    _native.lib()          # raises if the library is missing: no fallback
+
+
+def sim_of(P, precision, kernel=0):
+    from paper_1302_7104_amd.sim import Sim
+    return Sim(P, precision=precision, kernel=kernel)
+
+
+def grid_of(P):
+    return O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par)
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def start(P, F, precision, noise_seed=None, amp=1e-3, kernel=0):
+    """Same initial state on both sides: f^eq(fields) times (1 + noise)."""
+    s = sim_of(P, precision, kernel)
+    s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    f_or = O.init_feq(grid_of(P), **F)
+    if noise_seed is not None:
+        nz = W.noise((33, P.nr, P.nth), amp, noise_seed)
+        s.state.mul_(torch.as_tensor(1.0 + nz, device=s.device, dtype=s.dtype))
+        f_or = f_or * (1.0 + nz)
+    return s, f_or
+
+
+def smooth_problem(nr, nth, bc, seed):
+    return W.smooth_random(nr, nth, seed=seed, amp=0.05, bc=(bc[0][0], bc[1][0]),
+                           bc_par=(bc[0][1], bc[1][1]))
+
+
+BCS = [
+    ((W.WALL, (0.2, 0, 0, 0)), (W.WALL, (-0.1, 0, 0, 0))),
+    ((W.INFLOW, (1.1, 0.05, 0.02, 1.05)), (W.EXTRAPOLATE, (0, 0, 0, 0))),
+    ((W.EXTRAPOLATE, (0, 0, 0, 0)), (W.INFLOW, (0.9, -0.03, 0.1, 0.95))),
+]
+
+
+# --------------------------------------------------------------------------
+def test_init_state_matches_oracle():
+    P, F = smooth_problem(37, 250, BCS[0], 1)
+    for prec, tol in ((64, 1e-14), (32, 1e-7)):
+        s = sim_of(P, prec)
+        s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        got = s.state.double().cpu().numpy()
+        want = O.init_feq(grid_of(P), **F)
+        assert rel(got, want) <= tol, (prec, rel(got, want))
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("kernel", [1, 0])
+def test_step_parity_fp64_small(bc, kernel):
+    P, F = smooth_problem(37, 250, bc, 2)
+    s, f0 = start(P, F, 64, noise_seed=3, kernel=kernel)
+    s.step(5)
+    got = s.state.cpu().numpy()
+    want, bad = O.step(grid_of(P), f0, 5)
+    assert bad == 0
+    assert rel(got, want) <= FP64_TOL, rel(got, want)
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_step_parity_fp32_small(bc):
+    P, F = smooth_problem(37, 250, bc, 4)
+    s, f0 = start(P, F, 32, noise_seed=5)
+    s.step(5)
+    got = s.state.double().cpu().numpy()
+    want, _ = O.step(grid_of(P), f0, 5)
+    assert rel(got, want) <= 2e-7, rel(got, want)
+
+
+def test_rotation_config_fp64_full():
+    P, F = W.rotation(64, 128, 200)
+    s, f0 = start(P, F, 64)
+    s.step(P.steps)
+    got = s.state.cpu().numpy()
+    g = grid_of(P)
+    want, _ = O.step(g, f0, P.steps)
+    assert rel(got, want) <= FP64_TOL, rel(got, want)
+    d = s.diagnostics_host()
+    dw = O.diagnostics(g, want)
+    assert abs(d[0] - dw[0]) <= 1e-13 * dw[0]
+    assert abs(d[3] - dw[3]) <= 1e-13 * dw[3]
+    assert d[7] == P.steps
+
+
+FULL = {"shock_tube": (W.shock_tube, (512, 1024)),
+        "richtmyer_meshkov": (W.richtmyer_meshkov, (2048, 4096)),
+        "kelvin_helmholtz": (W.kelvin_helmholtz, (4096, 8192))}
+
+
+def noise_floor(g, f0, steps, seed=0):
+    """How far two FP64 oracle trajectories drift apart when one of them is
+    perturbed by one unit in the last place, at random, after every step: the
+    amplification of rounding-level differences that the problem itself shows."""
+    a, _ = O.step(g, f0, steps)
+    b = f0.copy()
+    rng = np.random.default_rng(seed)
+    for _ in range(steps):
+        b, _ = O.step(g, b, 1)
+        b *= 1.0 + 2.0 ** -52 * rng.uniform(-1.0, 1.0, b.shape)
+    return a, rel(b, a)
+
+
+@pytest.mark.parametrize("name", sorted(FULL))
+def test_config_recipes_reduced_fp64_50_steps(name):
+    """Each recipe on 128 x 256 (dt/tau and Courant numbers of its full size),
+    50 steps: FP64 parity at 1e-12."""
+    make, full = FULL[name]
+    P, F = W.reduced(make, 128, 256, 50, full)
+    s, f0 = start(P, F, 64)
+    s.step(50)
+    got = s.state.cpu().numpy()
+    want, bad = O.step(grid_of(P), f0, 50)
+    assert bad == 0
+    assert rel(got, want) <= FP64_TOL, (name, rel(got, want))
+
+
+@pytest.mark.parametrize("name", sorted(FULL))
+def test_config_recipes_reduced_fp64_long(name):
+    """300 steps: FP64 error within 1e-12 or, where the flow amplifies
+    rounding differences (shear layers, shocks), within 10x the drift of two
+    oracle runs that differ by one ulp of noise per step."""
+    make, full = FULL[name]
+    P, F = W.reduced(make, 128, 256, 300, full)
+    s, f0 = start(P, F, 64)
+    s.step(300)
+    got = s.state.cpu().numpy()
+    want, floor = noise_floor(grid_of(P), f0, 300)
+    err = rel(got, want)
+    print(f"{name}: GPU FP64 vs oracle {err:.3e}, oracle ulp-noise drift {floor:.3e}")
+    assert np.isfinite(got).all()
+    assert err <= max(FP64_TOL, 10.0 * floor), (name, err, floor)
+
+
+def test_shock_tube_reduced_fp32_error():
+    make, full = FULL["shock_tube"]
+    P, F = W.reduced(make, 128, 256, 300, full)
+    s, f0 = start(P, F, 32)
+    s.step(300)
+    rho = s.fields()["rho"].cpu().numpy()
+    want, _ = O.step(grid_of(P), f0, 300)
+    rw, _, _, Tw = O.fields(grid_of(P), want)
+    err = np.abs(rho - rw) / rw
+    print(f"shock tube 128x256, 300 steps: FP32 max rel density error {err.max():.3e}")
+    assert err.max() <= 1e-4, err.max()
+
+
+# --------------------------------------------------------------------------
+# Full-size configurations, one step, in the launch configuration the
+# benchmark times; the oracle evaluates sampled nodes one by one.
+
+def sample_nodes(nr, nth, n, seed):
+    rng = np.random.default_rng(seed)
+    pts = [(i, j) for i in (0, 1, 2, nr - 3, nr - 2, nr - 1) for j in (0, 1, nth // 2, nth - 2, nth - 1)]
+    pts += [(int(a), int(b)) for a, b in zip(rng.integers(0, nr, n), rng.integers(0, nth, n))]
+    return pts
+
+
+@pytest.mark.parametrize("name,prec", [
+    ("kelvin_helmholtz_4096x8192", 32),
+    ("richtmyer_meshkov_2048x4096", 32),
+    ("shock_tube_512x1024", 64),
+    ("adjoint_rm_1024x2048", 64),
+])
+def test_full_size_one_step_sampled(name, prec):
+    P, F = W.CONFIGS[name]()
+    s = sim_of(P, prec)
+    s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    del F
+    f0 = s.state.clone()
+    s.step(1)
+    nodes = sample_nodes(P.nr, P.nth, 1500, 9)
+    idx_i = torch.tensor([a for a, _ in nodes], device=s.device)
+    idx_j = torch.tensor([b for _, b in nodes], device=s.device)
+    got = s.state[:, idx_i, idx_j].double().cpu().numpy().T
+    f0h = f0.cpu().numpy()
+    del f0
+    s.close()
+    torch.cuda.empty_cache()
+    want = O.step_sample(grid_of(P), f0h, nodes)
+    scale = np.abs(want).sum(1, keepdims=True)
+    err = np.abs(got - want) / scale
+    tol = 1e-14 if prec == 64 else 1e-6
+    assert err.max() <= tol, (name, err.max())
+
+
+# --------------------------------------------------------------------------
+def test_bitwise_deterministic():
+    P, F = W.kelvin_helmholtz(64, 384, 20)
+    outs = []
+    for _ in range(2):
+        s = sim_of(P, 32)
+        s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        s.step(20)
+        outs.append(s.state.cpu().numpy().copy())
+        d = s.diagnostics_host()
+        outs.append(d)
+    assert np.array_equal(outs[0], outs[2])
+    assert np.array_equal(outs[1], outs[3])
+
+
+def test_node_and_strip_kernels_bitwise_equal():
+    from paper_1302_7104_amd import _native as N
+    for prec in (32, 64):
+        P, F = W.kelvin_helmholtz(48, 1000, 10)
+        res = []
+        for kernel in (N.KERNEL_NODE, N.KERNEL_AUTO):
+            s = sim_of(P, prec, kernel)
+            s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+            s.step(10)
+            res.append(s.state.cpu().numpy())
+        assert np.array_equal(res[0], res[1]), prec
+
+
+def test_init_rejects_bad_fields():
+    from paper_1302_7104_amd._native import PclbError
+    P, F = smooth_problem(8, 16, BCS[0], 6)
+    s = sim_of(P, 64)
+    rho = F["rho"].copy()
+    rho[3, 4] = -1.0
+    with pytest.raises(PclbError, match="EINVAL"):
+        s.init_state(rho, F["ur"], F["ut"], F["T"])
+
+
+def test_nonfinite_state_reported():
+    from paper_1302_7104_amd._native import PclbError
+    P, F = smooth_problem(8, 16, BCS[0], 7)
+    s = sim_of(P, 32)
+    s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    s.state[5, 2, 3] = float("nan")
+    with pytest.raises(PclbError, match="ENONFINITE"):
+        s.diagnostics_host()
+
+
+def test_diagnostics_match_oracle():
+    P, F = smooth_problem(33, 96, BCS[1], 8)
+    s, f0 = start(P, F, 64, noise_seed=9)
+    d = s.diagnostics_host()
+    dw = O.diagnostics(grid_of(P), f0)
+    np.testing.assert_allclose(d[:4], dw[:4], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(d[4:6], dw[4:6], rtol=1e-13)
+    assert d[6] == 0
+
+
+def test_fields_match_oracle():
+    P, F = smooth_problem(33, 96, BCS[2], 10)
+    s, f0 = start(P, F, 64, noise_seed=11)
+    fl = s.fields()
+    want = O.fields(grid_of(P), f0)
+    for k, w in zip(("rho", "ur", "ut", "T"), want):
+        np.testing.assert_allclose(fl[k].cpu().numpy(), w, rtol=1e-13, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Adjoint
+
+@pytest.mark.parametrize("bc", BCS)
+def test_adjoint_step_parity(bc):
+    P, F = smooth_problem(21, 70, bc, 12)
+    g = grid_of(P)
+    for prec, tol in ((64, 1e-12), (32, 1e-5), (64, 1e-12), (32, 1e-5)):
+        s, f0 = start(P, F, prec, noise_seed=13, amp=1e-2)
+        lam = W.noise((33, P.nr, P.nth), 1.0, 14)
+        lam_in = lam.astype(np.float32).astype(np.float64) if prec == 32 else lam
+        lam_t = torch.as_tensor(lam, dtype=s.dtype, device=s.device).contiguous()
+        out = torch.full_like(lam_t, float("nan"))    # unwritten entries stay NaN
+        s.adjoint_step(s.state, lam_t, out)
+        got = out.double().cpu().numpy()
+        assert np.isfinite(got).all()
+        want = O.adjoint_step(g, f0, lam_in)
+        assert rel(got, want) <= tol, (prec, rel(got, want))
+
+
+def test_adjoint_init_parity():
+    P, F = smooth_problem(15, 40, BCS[0], 15)
+    s = sim_of(P, 64)
+    lam = W.noise((33, P.nr, P.nth), 1.0, 16)
+    d = s.adjoint_init(torch.as_tensor(lam, device=s.device), F["rho"], F["ur"], F["ut"], F["T"])
+    want = O.adjoint_init(grid_of(P), F["rho"], F["ur"], F["ut"], F["T"], lam)
+    for a, b in zip(d, want):
+        assert rel(a.cpu().numpy(), b) <= 1e-13
+
+
+def band_weight(P):
+    R, _ = W.node_coords(P.nr, P.nth, P.r1, P.r2)
+    return ((R > 1.1) & (R < 1.5)) * R * P.dr * P.dth
+
+
+def oracle_states(g, f0, n):
+    states = [f0]
+    for _ in range(n):
+        states.append(O.step(g, states[-1], 1)[0])
+    return states
+
+
+def test_adjoint_chain_on_oracle_trajectory():
+    """The GPU adjoint step applied backwards along the oracle's own FP64
+    trajectory of the Richtmyer-Meshkov recipe (sharp shock, uniform regions,
+    inflow and wall boundaries) reproduces the oracle's adjoint chain."""
+    P, F = W.richtmyer_meshkov(24, 64, 30)
+    n = 30
+    g = grid_of(P)
+    states = oracle_states(g, O.init_feq(g, **F), n)
+    lam0 = np.broadcast_to(2.0 * states[-1].sum(0) * band_weight(P), (33, P.nr, P.nth)).copy()
+    s = sim_of(P, 64)
+    lam_g = torch.as_tensor(lam0, device=s.device)
+    out = torch.empty_like(lam_g)
+    lam_o = lam0
+    for t in reversed(range(n)):
+        ft = torch.as_tensor(states[t], device=s.device)
+        s.adjoint_step(ft, lam_g, out)
+        lam_g, out = out, lam_g
+        lam_o = O.adjoint_step(g, states[t], lam_o)
+    assert rel(lam_g.cpu().numpy(), lam_o) <= 1e-12, rel(lam_g.cpu().numpy(), lam_o)
+
+
+def test_evolve_gradient_matches_oracle_chain():
+    """Gradient of J = sum_band rho^2 r dr dtheta after n steps with respect to
+    the initial density on a smooth state (no exact ties of the MWB switch):
+    GPU autograd with checkpoint-recompute vs the oracle's adjoint chain."""
+    from paper_1302_7104_amd.sim import Evolve, InitState
+    P, F = smooth_problem(24, 64, BCS[1], 17)
+    n = 30
+    g = grid_of(P)
+    s = sim_of(P, 64)
+    rho = torch.as_tensor(F["rho"], device=s.device).requires_grad_(True)
+    others = [torch.as_tensor(F[k], device=s.device) for k in ("ur", "ut", "T")]
+    f0 = InitState.apply(s, rho, *others)
+    fn = Evolve.apply(s, f0, n, 8)
+    band = torch.as_tensor(band_weight(P), device=s.device)
+    J = ((fn.sum(0) ** 2) * band).sum()
+    J.backward()
+    got = rho.grad.cpu().numpy()
+    states = oracle_states(g, O.init_feq(g, **F), n)
+    lam = np.broadcast_to(2.0 * states[-1].sum(0) * band.cpu().numpy(), (33, P.nr, P.nth)).copy()
+    for t in reversed(range(n)):
+        lam = O.adjoint_step(g, states[t], lam)
+    want = O.adjoint_init(g, F["rho"], F["ur"], F["ut"], F["T"], lam)[0]
+    assert rel(got, want) <= 1e-11, rel(got, want)
+
+
+def test_evolve_checkpointing_matches_stored_trajectory():
+    """Checkpoint-recompute gives bitwise the same gradient as a backward pass
+    over stored states (FP32)."""
+    from paper_1302_7104_amd.sim import Evolve
+    P, F = W.richtmyer_meshkov(32, 96, 23)
+    s = sim_of(P, 32)
+    s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    f0 = s.state.clone()
+    g_out = torch.as_tensor(W.noise((33, P.nr, P.nth), 1.0, 18), dtype=torch.float32, device=s.device)
+    x = f0.clone().requires_grad_(True)
+    Evolve.apply(s, x, 23, 5).backward(g_out)
+    got = x.grad.clone()
+    states = [f0.clone()]
+    for _ in range(23):
+        nxt = torch.empty_like(f0)
+        s.step_into(states[-1], nxt)
+        states.append(nxt)
+    lam = g_out.clone()
+    out = torch.empty_like(lam)
+    for t in reversed(range(23)):
+        s.adjoint_step(states[t], lam, out)
+        lam, out = out, lam
+    assert torch.equal(got, lam)

@@ -532,3 +532,16 @@ def test_adjoint_init_fd():
         # perturbing every node at once: the dot product with ones
         fd = np.sum(lam * (O.init_feq(g, **Fp) - O.init_feq(g, **Fm))) / (2 * h)
         assert abs(fd - d[n].sum()) < 1e-6 * (1 + abs(fd))
+
+
+def test_step_sample_matches_full_step():
+    # The sampled evaluation used for very large grids equals the full step.
+    P, F = W.smooth_random(7, 24, seed=31, bc=(W.INFLOW, W.EXTRAPOLATE),
+                           bc_par=((1.05, 0.02, 0.01, 1.02), (0, 0, 0, 0)))
+    g = grid_of(P)
+    f0 = O.init_feq(g, **F) * (1 + 1e-3 * W.noise((33, 7, 24), 1.0, 32))
+    full, _ = O.step(g, f0, 1)
+    nodes = [(i, j) for i in range(7) for j in (0, 1, 5, 22, 23)]
+    s = O.step_sample(g, f0, nodes)
+    for n, (i, j) in enumerate(nodes):
+        np.testing.assert_array_equal(s[n], full[:, i, j])
