@@ -94,6 +94,7 @@ def lib():
         L.or_mwb_term.restype = ctypes.c_double
         L.or_mwb_grad.argtypes = [ctypes.c_double, _D, _D]
         L.or_set_kink.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.or_set_tie.argtypes = [ctypes.c_double]
         L.or_step.argtypes = [G, _D, _D, ctypes.c_int32]
         L.or_step.restype = ctypes.c_int
         L.or_step_sample.argtypes = [G, _D, _I, ctypes.c_int32, _D]
@@ -168,6 +169,12 @@ def mwb_grad(C, psi5) -> np.ndarray:
 def set_kink(h1: float, h2: float) -> None:
     """(dh/d(delta), dh/d(delta')) used by the adjoint where delta = delta' = 0."""
     lib().or_set_kink(float(h1), float(h2))
+
+
+def set_tie(eps: float) -> None:
+    """Relative size below which an upwind difference counts as zero when the
+    adjoint picks its derivative branch (1e-13 by default)."""
+    lib().or_set_tie(float(eps))
 
 
 def step(grid: Grid, f: np.ndarray, nsteps: int) -> tuple[np.ndarray, int]:

@@ -200,31 +200,47 @@ template <class T> T mwb_term(double C, const T psi[5], int s_mode) {
   return (C + 0.5 * C * (1.0 - std::fabs(C)) * (1.0 - S) * (1.0 - eta)) * delta;
 }
 
-// Partial derivatives of mwb_term with respect to psi_{j-2..j+2}.  Away from
-// delta = 0 they come from forward-mode differentiation of the formula (with
-// sgn(0) = 0 inside |eta|).  At delta = 0 the term is C delta + C(1-|C|) h with
-// h = (delta - delta') |delta| / (|delta| + |delta'|): dh/d(delta) = 0 and
-// dh/d(delta') = 0 when delta' != 0.  When delta' = 0 as well, h is not
-// differentiable; (dh/d(delta), dh/d(delta')) is then taken as KINK_H.
+// Partial derivatives of mwb_term with respect to psi_{j-2..j+2}, written as
+// derivatives of the term in (delta, delta') mapped back to the stencil.  The
+// term is not differentiable where delta or delta' vanishes, and there the
+// derivative branch would be decided by rounding noise; so a difference whose
+// size is within TIE_EPS times the stencil's magnitude counts as zero.  With
+// delta = 0 the term is C delta + C(1-|C|) h, h = (delta - delta') |delta| /
+// (|delta| + |delta'|): dh/d(delta) = dh/d(delta') = 0 when delta' != 0, and
+// (dh/d(delta), dh/d(delta')) = KINK_H when delta' = 0 too.  Elsewhere the
+// derivatives come from forward-mode differentiation of the paper's form
+// (sgn(0) = 0 inside |eta|).
 double KINK_H[2] = {1.0, 0.0};
+double TIE_EPS = 1e-13;
 
 void mwb_grad(double C, const double psi[5], double g[5]) {
   for (int n = 0; n < 5; ++n) g[n] = 0;
-  double delta, dprime;
-  if (C >= 0) { delta = psi[2] - psi[1]; dprime = psi[1] - psi[0]; }
-  else        { delta = psi[3] - psi[2]; dprime = psi[4] - psi[3]; }
+  const bool back = C >= 0;
+  double delta = back ? psi[2] - psi[1] : psi[3] - psi[2];
+  double dprime = back ? psi[1] - psi[0] : psi[4] - psi[3];
+  double mag = back ? std::fabs(psi[0]) + std::fabs(psi[1]) + std::fabs(psi[2])
+                    : std::fabs(psi[2]) + std::fabs(psi[3]) + std::fabs(psi[4]);
+  double thr = TIE_EPS * mag;
+  if (std::fabs(delta) <= thr) delta = 0.0;
+  if (std::fabs(dprime) <= thr) dprime = 0.0;
+  double K = C * (1.0 - std::fabs(C));
+  double dd, ddp;   // d term / d delta, d term / d delta'
   if (delta == 0.0) {
-    double K = C * (1.0 - std::fabs(C));
     double h1 = dprime == 0.0 ? KINK_H[0] : 0.0, h2 = dprime == 0.0 ? KINK_H[1] : 0.0;
-    double d_delta = C + K * h1, d_dprime = K * h2;
-    if (C >= 0) { g[2] += d_delta; g[1] -= d_delta; g[1] += d_dprime; g[0] -= d_dprime; }
-    else        { g[3] += d_delta; g[2] -= d_delta; g[4] += d_dprime; g[3] -= d_dprime; }
-    return;
+    dd = C + K * h1;
+    ddp = K * h2;
+  } else {
+    Dual<2> D(delta), Dp(dprime);
+    D.d[0] = 1.0;
+    Dp.d[1] = 1.0;
+    Dual<2> eta = Dp / D;
+    Dual<2> S = (dabs(eta) - 1.0) / (dabs(eta) + 1.0);
+    Dual<2> t = (C + 0.5 * K * (1.0 - S) * (1.0 - eta)) * D;
+    dd = t.d[0];
+    ddp = t.d[1];
   }
-  Dual<5> p[5];
-  for (int n = 0; n < 5; ++n) { p[n] = Dual<5>(psi[n]); p[n].d[n] = 1.0; }
-  Dual<5> t = mwb_term(C, p, 0);
-  for (int n = 0; n < 5; ++n) g[n] = t.d[n];
+  if (back) { g[2] += dd; g[1] += -dd + ddp; g[0] += -ddp; }
+  else      { g[3] += dd - ddp; g[2] += -dd; g[4] += ddp; }
 }
 
 }  // namespace
@@ -417,6 +433,9 @@ void or_mwb_grad(double C, const double* psi, double* g) { mwb_grad(C, psi, g); 
 
 // Choice of (dh/d(delta), dh/d(delta')) where both upwind differences vanish.
 void or_set_kink(double h1, double h2) { KINK_H[0] = h1; KINK_H[1] = h2; }
+
+// Relative size below which an upwind difference counts as zero in the adjoint.
+void or_set_tie(double eps) { TIE_EPS = eps; }
 
 
 // Eq. combined_scheme applied nsteps times: f_out = f after nsteps steps.

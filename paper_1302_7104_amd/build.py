@@ -15,6 +15,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off (see the design notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c only within one source expression, so that a device
+    # function inlined into two kernels rounds identically in both
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

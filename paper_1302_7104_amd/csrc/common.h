@@ -9,6 +9,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Every helper below is also compiled for the host, where a CPU emulation of
+// the per-node update runs the same arithmetic for the CPU test-suite.
+#define PCLB_HD __host__ __device__
+
 namespace pclb {
 
 constexpr int NQ = 33;
@@ -35,13 +39,52 @@ __host__ __device__ constexpr double vx_q(int q) { return speed(k_of(q)) * cos_d
 __host__ __device__ constexpr double vy_q(int q) { return speed(k_of(q)) * sin_d(d_of(q)); }
 __host__ __device__ constexpr double v2_q(int q) { return speed(k_of(q)) * speed(k_of(q)); }
 
+// Weights F_k(E) of the octagon model (Eqs. F_k with the first row of Table I,
+// B = (B0, B1, B2, B3, B4) = (8, -1/4, 1, -6, 48), suffixes {k+l} = mod{k+l, 4})
+// as polynomials F_k(E) = E (c0 + E (c1 + E (c2 + E c3))):
+//   c0 = B1 e3 / den, c1 = B2 e2 / den, c2 = B3 e1 / den, c3 = B4 / den,
+// e1, e2, e3 the elementary symmetric sums of the other three v_l^2 and
+// den = v_k^2 prod_l (v_k^2 - v_l^2).  Evaluated at compile time.
+struct WeightPoly {
+  double c[NK][4];
+};
+constexpr WeightPoly make_weight_poly() {
+  WeightPoly w{};
+  const double B1 = -0.25, B2 = 1.0, B3 = -6.0, B4 = 48.0;
+  double x[NK + 1] = {};
+  for (int k = 0; k <= NK; ++k) x[k] = speed(k) * speed(k);
+  for (int k = 1; k <= NK; ++k) {
+    int o[3] = {};
+    for (int l = 1; l <= 3; ++l) o[l - 1] = (k + l <= NK) ? k + l : k + l - NK;
+    const double a = x[o[0]], b = x[o[1]], c = x[o[2]];
+    const double den = x[k] * (x[k] - a) * (x[k] - b) * (x[k] - c);
+    w.c[k - 1][0] = B1 * a * b * c / den;
+    w.c[k - 1][1] = B2 * (a * b + b * c + c * a) / den;
+    w.c[k - 1][2] = B3 * (a + b + c) / den;
+    w.c[k - 1][3] = B4 / den;
+  }
+  return w;
+}
+template <int K, int N> struct WC {
+  static constexpr double v = make_weight_poly().c[K][N];
+};
+// F_k(E) for k = K + 1.
+template <int K>
+__host__ __device__ inline double weight_k(double E) {
+  return E * (WC<K, 0>::v + E * (WC<K, 1>::v + E * (WC<K, 2>::v + E * WC<K, 3>::v)));
+}
+// dF_k/dE for k = K + 1.
+template <int K>
+__host__ __device__ inline double weight_k_prime(double E) {
+  return WC<K, 0>::v + E * (2.0 * WC<K, 1>::v + E * (3.0 * WC<K, 2>::v + E * 4.0 * WC<K, 3>::v));
+}
+
 // Everything a step launch needs besides the state buffers.
 struct Tables {
   int32_t nr, nth;
   double dt_dr;        // dt / dr
   double dt_dth;       // dt / dtheta
   double e;            // exp(-dt / tau), computed on the host in double
-  double fc[NK][4];    // F_k(E) = E (c0 + E (c1 + E (c2 + E c3))), k = 1..4 at [k-1]
   const double* cth;   // cos(theta_j), j = 0..nth-1
   const double* sth;   // sin(theta_j)
   const double* rinv;  // 1 / r_i, i = 0..nr-1
@@ -73,17 +116,15 @@ struct EqCoef {
   double p[4];         // u . e_d for d = 0..3 (d + 4 is the negative)
 };
 
-__device__ inline void eq_setup(const Tables& T, double rho, double ux, double uy, double E,
+PCLB_HD inline void eq_setup(const Tables& T, double rho, double ux, double uy, double E,
                                 EqCoef& c) {
   double iE = 1.0 / E;
-  double sum = 0.0;
-#pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    double F = E * (T.fc[k][0] + E * (T.fc[k][1] + E * (T.fc[k][2] + E * T.fc[k][3])));
-    c.rF[k + 1] = rho * F;
-    sum += F;
-  }
-  c.rF[0] = rho * (1.0 - 8.0 * sum);
+  const double F1 = weight_k<0>(E), F2 = weight_k<1>(E), F3 = weight_k<2>(E), F4 = weight_k<3>(E);
+  c.rF[1] = rho * F1;
+  c.rF[2] = rho * F2;
+  c.rF[3] = rho * F3;
+  c.rF[4] = rho * F4;
+  c.rF[0] = rho * (1.0 - 8.0 * (((F1 + F2) + F3) + F4));
   double u2 = ux * ux + uy * uy;
   double a = 0.5 * u2 * iE;
   double g = 1.0 - a;
@@ -99,29 +140,94 @@ __device__ inline void eq_setup(const Tables& T, double rho, double ux, double u
   c.p[3] = (uy - ux) * RSQRT2;
 }
 
-__device__ inline double eq_val(const EqCoef& c, int k, int d) {
+PCLB_HD inline double eq_val(const EqCoef& c, int k, int d) {
   double pd = d < 4 ? c.p[d] : -c.p[d - 4];
   double w = speed(k) * pd;
   return c.rF[k] * (c.A0 + w * (c.A1 + w * (c.A2 + w * (c.A3 + w * c.A4))));
 }
 
 // Linear moments of one node: rho, j_x, j_y and eps = sum f v^2 / 2; then the
-// macroscopic u and E = eps / rho - u^2 / 2 (Eqs. moment1-moment3).
-__device__ inline void node_macros(const double* f, double& rho, double& ux, double& uy,
+// macroscopic u and E = eps / rho - u^2 / 2 (Eqs. moment1-moment3).  The sums
+// are grouped by speed: per group k the plain sum S_k and the projections
+// X_k = sum_d cos(d pi/4) f_kd, Y_k = sum_d sin(d pi/4) f_kd.
+PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double& uy,
                                    double& E) {
-  double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
+  double r = f[0], jx = 0.0, jy = 0.0, eps = 0.0;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    r += f[q];
-    jx += f[q] * vx_q(q);
-    jy += f[q] * vy_q(q);
-    eps += f[q] * v2_q(q);
+  for (int k = 1; k <= NK; ++k) {
+    const double* g = f + qidx(k, 0);
+    const double S = ((g[0] + g[4]) + (g[2] + g[6])) + ((g[1] + g[5]) + (g[3] + g[7]));
+    const double X = (g[0] - g[4]) + ((g[1] - g[5]) - (g[3] - g[7])) * RSQRT2;
+    const double Y = (g[2] - g[6]) + ((g[1] - g[5]) + (g[3] - g[7])) * RSQRT2;
+    r += S;
+    jx += speed(k) * X;
+    jy += speed(k) * Y;
+    eps += speed(k) * speed(k) * S;
   }
   rho = r;
-  double ir = 1.0 / r;
+  const double ir = 1.0 / r;
   ux = jx * ir;
   uy = jy * ir;
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
+}
+
+// Relaxed values of the opposite pair (k, d) and (k, d + 4), d = 0..3:
+// f^eq + (f - f^eq) e written as e f + (1 - e) f^eq, with f^eq = rho F_k P(+-w)
+// and P split into its even and odd parts in w.
+template <class R>
+PCLB_HD inline void relax_pair(const EqCoef& c, double e, double one_m_e, int k, int d, R fp, R fm,
+                                  R& rp, R& rm) {
+  const double w = speed(k) * c.p[d];
+  const double w2 = w * w;
+  const double ev = c.A0 + w2 * (c.A2 + w2 * c.A4);
+  const double od = w * (c.A1 + w2 * c.A3);
+  const double s = one_m_e * c.rF[k];
+  const double gp = s * (ev + od), gm = s * (ev - od);
+  if constexpr (sizeof(R) == 8) {
+    rp = fma((double)fp, e, gp);
+    rm = fma((double)fm, e, gm);
+  } else {
+    rp = fmaf(fp, (float)e, (float)gp);
+    rm = fmaf(fm, (float)e, (float)gm);
+  }
+}
+
+template <class R>
+PCLB_HD inline R relax_rest(const EqCoef& c, double e, double one_m_e, R f0) {
+  const double g = one_m_e * (c.rF[0] * c.A0);
+  if constexpr (sizeof(R) == 8) return fma((double)f0, e, g);
+  else return fmaf(f0, (float)e, (float)g);
+}
+
+// Direction geometry of one theta column: for each direction d, the sign of
+// v_r and v_theta (upwind side: bit d set = backward, i.e. v >= 0) and, per
+// d mod 4, |v_r| dt/dr and |v_theta| dt/dtheta per unit speed.  The Courant
+// numbers of velocity (k, d) are v_k * ar[d mod 4] and v_k * at[d mod 4] / r.
+template <class R> struct DirGeom {
+  R ar[4], at[4];
+  unsigned rback, tback;
+};
+template <class R>
+PCLB_HD inline void dir_geometry(double ct, double st, double dt_dr, double dt_dth, DirGeom<R>& g) {
+  g.rback = 0;
+  g.tback = 0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const double vr = cos_d(d) * ct + sin_d(d) * st;     // v_r / v_k
+    const double vt = sin_d(d) * ct - cos_d(d) * st;     // v_theta / v_k
+    if (vr >= 0.0) g.rback |= 1u << d;
+    if (vt >= 0.0) g.tback |= 1u << d;
+    if (d < 4) {
+      g.ar[d] = (R)(fabs(vr) * dt_dr);
+      g.at[d] = (R)(fabs(vt) * dt_dth);
+    }
+  }
+}
+// |C| and |C|(1 - |C|) from the speed and the per-unit-speed factor.
+template <class R>
+PCLB_HD inline void courant(R vk, R a, R& aC, R& K) {
+  aC = vk * a;
+  K = aC - aC * aC;
 }
 
 // ---------------------------------------------------------------------------
@@ -133,23 +239,135 @@ __device__ inline void node_macros(const double* f, double& rho, double& ux, dou
 // and is 0 in the limiter part when d1 = d2 = 0.
 template <class R> struct Lim;
 template <> struct Lim<double> {
-  __device__ static inline double ratio(double num, double den) {
+  PCLB_HD static inline double ratio(double num, double den) {
     return num / fmax(den, 2.2250738585072014e-308);
   }
 };
 template <> struct Lim<float> {
-  __device__ static inline float ratio(float num, float den) {
+  PCLB_HD static inline float ratio(float num, float den) {
+#if defined(__HIP_DEVICE_COMPILE__)
     return num * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f));
+#else
+    return num * (1.0f / fmaxf(den, 1.17549435e-38f));   // host emulation only
+#endif
   }
 };
 
 template <class R>
-__device__ inline R mwb_term(R absC, R K, R c, R u1, R u2) {
-  R d1 = c - u1;
-  R d2 = u1 - u2;
-  R den = (d1 < R(0) ? -d1 : d1) + (d2 < R(0) ? -d2 : d2);
-  R lim = Lim<R>::ratio((d1 - d2) * (d1 < R(0) ? -d1 : d1), den);
+PCLB_HD inline R mwb_term(R absC, R K, R c, R u1, R u2) {
+  const R d1 = c - u1;
+  const R d2 = u1 - u2;
+  const R a1 = sizeof(R) == 8 ? (R)fabs((double)d1) : (R)fabsf((float)d1);
+  const R a2 = sizeof(R) == 8 ? (R)fabs((double)d2) : (R)fabsf((float)d2);
+  const R lim = Lim<R>::ratio((d1 - d2) * a1, a1 + a2);
   return absC * d1 + K * lim;
+}
+
+// Limiter part (d1 - d2)|d1| / (|d1| + |d2|) of the MWB term.
+template <class R>
+PCLB_HD inline R mwb_lim(R d1, R d2) {
+  const R a1 = sizeof(R) == 8 ? (R)fabs((double)d1) : (R)fabsf((float)d1);
+  const R a2 = sizeof(R) == 8 ? (R)fabs((double)d2) : (R)fabsf((float)d2);
+  return Lim<R>::ratio((d1 - d2) * a1, a1 + a2);
+}
+
+// rel - T_r - T_theta for one velocity: the radial term from (c, u1r, u2r)
+// with (aCr, Kr), the azimuthal term from (c, u1t, u2t) with (aCt, Kt).
+template <class R>
+PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, R u1t, R u2t) {
+  const R d1r = c - u1r, d2r = u1r - u2r;
+  const R d1t = c - u1t, d2t = u1t - u2t;
+  const R lr = mwb_lim<R>(d1r, d2r);
+  const R lt = mwb_lim<R>(d1t, d2t);
+  R res = rel - aCr * d1r;
+  res = res - Kr * lr;
+  res = res - aCt * d1t;
+  res = res - Kt * lt;
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// Combined-scheme update of one node (Eq. combined_scheme): centre values fc,
+// radial neighbours row(q, di) at rows i+di (di = -2, -1, 1, 2; ghost rows
+// included) and azimuthal neighbours col(q, dj) at columns j+dj of row i.
+// res receives f at t + dt.
+template <class R, class RowFn, class ColFn>
+PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, const R* fc, RowFn row,
+                                ColFn col, R* res) {
+  double fd[NQ];
+  for (int q = 0; q < NQ; ++q) fd[q] = (double)fc[q];
+  double rho, ux, uy, E;
+  node_macros(fd, rho, ux, uy, E);
+  EqCoef ec;
+  eq_setup(T, rho, ux, uy, E, ec);
+  const double e = T.e, ome = 1.0 - T.e;
+  res[0] = relax_rest<R>(ec, e, ome, fc[0]);       // rest velocity: no convection
+  DirGeom<R> G;
+  dir_geometry(ct, st, T.dt_dr, T.dt_dth, G);
+  const R rinv = (R)T.rinv[i];
+  R atr[4];
+  for (int d = 0; d < 4; ++d) atr[d] = G.at[d] * rinv;
+#pragma unroll
+  for (int k = 1; k <= NK; ++k) {
+#pragma unroll
+    for (int d4 = 0; d4 < 4; ++d4) {
+      R rel[2];
+      relax_pair<R>(ec, e, ome, k, d4, fc[qidx(k, d4)], fc[qidx(k, d4 + 4)], rel[0], rel[1]);
+      R aCr, Kr, aCt, Kt;
+      courant<R>((R)speed(k), G.ar[d4], aCr, Kr);
+      courant<R>((R)speed(k), atr[d4], aCt, Kt);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int d = d4 + 4 * h;
+        const int q = qidx(k, d);
+        const int sr = ((G.rback >> d) & 1u) ? -1 : 1;   // upwind offset in r
+        const int sc = ((G.tback >> d) & 1u) ? -1 : 1;   // upwind offset in theta
+        res[q] = mwb_update<R>(rel[h], fc[q], aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt,
+                               col(q, sc), col(q, 2 * sc));
+      }
+    }
+  }
+}
+
+// Ghost layers of one wall and column (Sec. II.C, radial boundary condition):
+// from the macroscopic state of the wall row (f0) and the next row (f1),
+// extrapolate rho and E linearly and recursively (ghost0 = 2 row0 - row1,
+// ghost1 = 2 ghost0 - row0), set u per boundary kind, and return f^eq of
+// both ghost states in g0 and g1.
+template <class R>
+PCLB_HD inline void ghost_column(const Tables& T, const BCdev& bc, int side, double ct, double st,
+                                 const R* f0, const R* f1, R* g0, R* g1) {
+  double m[2][4];
+  double fl[NQ];
+  for (int q = 0; q < NQ; ++q) fl[q] = (double)f0[q];
+  node_macros(fl, m[0][0], m[0][1], m[0][2], m[0][3]);
+  for (int q = 0; q < NQ; ++q) fl[q] = (double)f1[q];
+  node_macros(fl, m[1][0], m[1][1], m[1][2], m[1][3]);
+  double prev[4] = {m[0][0], m[0][1], m[0][2], m[0][3]};
+  double pprev[4] = {m[1][0], m[1][1], m[1][2], m[1][3]};
+  const int kind = bc.kind[side];
+  for (int layer = 0; layer < 2; ++layer) {
+    double g[4];
+    for (int a = 0; a < 4; ++a) g[a] = 2.0 * prev[a] - pprev[a];
+    for (int a = 0; a < 4; ++a) { pprev[a] = prev[a]; prev[a] = g[a]; }
+    double rho = g[0], ux = g[1], uy = g[2], E = g[3];
+    if (kind == 0) {                   // WALL: u_r = 0, u_theta = omega r_g
+      const double ut = bc.p[side][0] * bc.rg[side][layer];
+      ux = -ut * st;
+      uy = ut * ct;
+    } else if (kind == 1) {            // INFLOW
+      rho = bc.p[side][0];
+      ux = bc.p[side][1] * ct - bc.p[side][2] * st;
+      uy = bc.p[side][1] * st + bc.p[side][2] * ct;
+      E = bc.p[side][3];
+    }                                  // EXTRAPOLATE keeps the extrapolated u
+    EqCoef c;
+    eq_setup(T, rho, ux, uy, E, c);
+    R* out = layer == 0 ? g0 : g1;
+    out[0] = (R)(c.rF[0] * c.A0);
+    for (int k = 1; k <= NK; ++k)
+      for (int d = 0; d < ND; ++d) out[qidx(k, d)] = (R)eq_val(c, k, d);
+  }
 }
 
 }  // namespace pclb

@@ -32,17 +32,11 @@ __device__ inline void feq_jac_setup(const Tables& T, double rho, double ux, dou
   J.rho = rho;
   J.ux = ux;
   J.uy = uy;
-  double sF = 0.0, sFp = 0.0;
-#pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    const double* a = T.fc[k];
-    J.F[k + 1] = E * (a[0] + E * (a[1] + E * (a[2] + E * a[3])));
-    J.Fp[k + 1] = a[0] + E * (2.0 * a[1] + E * (3.0 * a[2] + E * 4.0 * a[3]));
-    sF += J.F[k + 1];
-    sFp += J.Fp[k + 1];
-  }
-  J.F[0] = 1.0 - 8.0 * sF;
-  J.Fp[0] = -8.0 * sFp;
+  J.F[1] = weight_k<0>(E); J.F[2] = weight_k<1>(E); J.F[3] = weight_k<2>(E); J.F[4] = weight_k<3>(E);
+  J.Fp[1] = weight_k_prime<0>(E); J.Fp[2] = weight_k_prime<1>(E);
+  J.Fp[3] = weight_k_prime<2>(E); J.Fp[4] = weight_k_prime<3>(E);
+  J.F[0] = 1.0 - 8.0 * (((J.F[1] + J.F[2]) + J.F[3]) + J.F[4]);
+  J.Fp[0] = -8.0 * (((J.Fp[1] + J.Fp[2]) + J.Fp[3]) + J.Fp[4]);
   const double iE = 1.0 / E, iE2 = iE * iE, iE3 = iE2 * iE;
   const double a = 0.5 * (ux * ux + uy * uy) * iE, g = 1.0 - a;
   J.A0u = -0.5 * g * iE;
@@ -86,13 +80,18 @@ __device__ inline void to_moment_cotangent(double rho, double ux, double uy, dou
 }
 
 // Derivatives of T = |C| d1 + K h(d1, d2), d1 = c - u1, d2 = u1 - u2,
-// h = (d1 - d2)|d1| / (|d1| + |d2|), with respect to (c, u1, u2).  sgn(0) = 0;
-// at d1 = d2 = 0, (dh/dd1, dh/dd2) = (1, 0).
+// h = (d1 - d2)|d1| / (|d1| + |d2|), with respect to (c, u1, u2).  T is not
+// differentiable where d1 or d2 vanishes; a difference within `eps` times the
+// stencil's magnitude counts as zero there, so that rounding noise does not
+// pick the branch.  sgn(0) = 0; at d1 = d2 = 0, (dh/dd1, dh/dd2) = (1, 0).
 struct MwbD {
   double dc, du1, du2;
 };
-__device__ inline MwbD mwb_grad(double aC, double K, double c, double u1, double u2) {
-  const double d1 = c - u1, d2 = u1 - u2;
+__device__ inline MwbD mwb_grad(double aC, double K, double c, double u1, double u2, double eps) {
+  double d1 = c - u1, d2 = u1 - u2;
+  const double thr = eps * (fabs(c) + fabs(u1) + fabs(u2));
+  if (fabs(d1) <= thr) d1 = 0.0;
+  if (fabs(d2) <= thr) d2 = 0.0;
   const double a1 = fabs(d1), a2 = fabs(d2), D = a1 + a2;
   double h1 = 1.0, h2 = 0.0;
   if (D != 0.0) {
@@ -108,6 +107,12 @@ __device__ inline MwbD mwb_grad(double aC, double K, double c, double u1, double
   r.du2 = -K * h2;
   return r;
 }
+
+// Tie threshold per storage precision: a few hundred ulps of the stored values
+// (rounding differences of f^eq scale with sum |f| / rho, up to about 16 here).
+template <class R> struct TieEps;
+template <> struct TieEps<double> { static constexpr double value = 1e-13; };
+template <> struct TieEps<float> { static constexpr double value = 1e-5; };
 
 template <class R>
 __device__ inline double fetch_f(const R* __restrict__ f, const R* __restrict__ ghost, int q, int i,
@@ -144,6 +149,7 @@ __global__ void __launch_bounds__(128) ghost_adjoint_kernel(Tables T, BCdev bc, 
   const int gsgn = side == 0 ? -1 : 1;     // direction from the wall row into the ghosts
   const double ct = T.cth[j], st = T.sth[j];
   const int kind = bc.kind[side];
+  constexpr double TE = TieEps<R>::value;
   // macroscopic state of the two real rows
   double m0[4], m1[4];
   {
@@ -185,8 +191,8 @@ __global__ void __launch_bounds__(128) ghost_adjoint_kernel(Tables T, BCdev bc, 
         const double g1 = fetch_f(f, ghost, q, i0 + 2 * gsgn, j, nr, nth, plane);
         const double lw = (double)lam[q * plane + (size_t)i0 * nth + j];
         const double l1 = (double)lam[q * plane + (size_t)i1 * nth + j];
-        const MwbD a = mwb_grad(aC, K, fw, g0, g1);   // wall row: u1 = ghost 0, u2 = ghost 1
-        const MwbD b = mwb_grad(aC, K, f1, fw, g0);   // next row: u2 = ghost 0
+        const MwbD a = mwb_grad(aC, K, fw, g0, g1, TE);   // wall row: u1 = ghost 0, u2 = ghost 1
+        const MwbD b = mwb_grad(aC, K, f1, fw, g0, TE);   // next row: u2 = ghost 0
         feq_jac_accum<q>(J0, -lw * a.du1 - l1 * b.du2, G0);
         feq_jac_accum<q>(J1, -lw * a.du2, G1);
       }
@@ -227,6 +233,7 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
   const size_t plane = (size_t)nr * nth;
   const size_t c0 = (size_t)i * nth + j;
   const double e = T.e;
+  constexpr double TE = TieEps<R>::value;
   // moment cotangent of this node from the relaxation's f^eq
   double gM[4];
   {
@@ -282,17 +289,17 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
       const double r3 = fetch_f(f, ghost, q, i + 1, j, nr, nth, plane);
       const double r4 = fetch_f(f, ghost, q, i + 2, j, nr, nth, plane);
       // m as centre
-      acc -= lq * mwb_grad(aC, K, r2, back ? r1 : r3, back ? r0 : r4).dc;
+      acc -= lq * mwb_grad(aC, K, r2, back ? r1 : r3, back ? r0 : r4, TE).dc;
       // m as first upwind neighbour of n1 = i + 1 (backward) or i - 1 (forward)
       const int n1 = back ? i + 1 : i - 1;
       if (n1 >= 0 && n1 < nr) {
-        const MwbD g = back ? mwb_grad(aC, K, r3, r2, r1) : mwb_grad(aC, K, r1, r2, r3);
+        const MwbD g = back ? mwb_grad(aC, K, r3, r2, r1, TE) : mwb_grad(aC, K, r1, r2, r3, TE);
         acc -= (double)lam[q * plane + (size_t)n1 * nth + j] * g.du1;
       }
       // m as second upwind neighbour of n2 = i + 2 (backward) or i - 2 (forward)
       const int n2 = back ? i + 2 : i - 2;
       if (n2 >= 0 && n2 < nr) {
-        const MwbD g = back ? mwb_grad(aC, K, r4, r3, r2) : mwb_grad(aC, K, r0, r1, r2);
+        const MwbD g = back ? mwb_grad(aC, K, r4, r3, r2, TE) : mwb_grad(aC, K, r0, r1, r2, TE);
         acc -= (double)lam[q * plane + (size_t)n2 * nth + j] * g.du2;
       }
     }
@@ -306,29 +313,29 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
       vt = -vx * sn[0] + vy * cs[0];
       if (vt < 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[0]] * mwb_grad(aC, K, t0, t1, t2).du2;
+        acc -= (double)lp[jj[0]] * mwb_grad(aC, K, t0, t1, t2, TE).du2;
       }
       // s = 1: n = j - 1, forward (m = u1)
       vt = -vx * sn[1] + vy * cs[1];
       if (vt < 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[1]] * mwb_grad(aC, K, t1, t2, t3).du1;
+        acc -= (double)lp[jj[1]] * mwb_grad(aC, K, t1, t2, t3, TE).du1;
       }
       // s = 2: n = m (m is the centre)
       vt = -vx * sn[2] + vy * cs[2];
       aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-      acc -= lq * (vt >= 0.0 ? mwb_grad(aC, K, t2, t1, t0) : mwb_grad(aC, K, t2, t3, t4)).dc;
+      acc -= lq * (vt >= 0.0 ? mwb_grad(aC, K, t2, t1, t0, TE) : mwb_grad(aC, K, t2, t3, t4, TE)).dc;
       // s = 3: n = j + 1, backward (m = u1)
       vt = -vx * sn[3] + vy * cs[3];
       if (vt >= 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[3]] * mwb_grad(aC, K, t3, t2, t1).du1;
+        acc -= (double)lp[jj[3]] * mwb_grad(aC, K, t3, t2, t1, TE).du1;
       }
       // s = 4: n = j + 2, backward (m = u2)
       vt = -vx * sn[4] + vy * cs[4];
       if (vt >= 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[4]] * mwb_grad(aC, K, t4, t3, t2).du2;
+        acc -= (double)lp[jj[4]] * mwb_grad(aC, K, t4, t3, t2, TE).du2;
       }
     }
     out[q * plane + c0] = (R)acc;

@@ -18,46 +18,19 @@ __global__ void __launch_bounds__(256) ghost_kernel(Tables T, BCdev bc, const R*
   int side = blockIdx.y;
   if (j >= T.nth) return;
   const size_t plane = (size_t)T.nr * T.nth;
-  int i0 = side == 0 ? 0 : T.nr - 1;
-  int i1 = side == 0 ? 1 : T.nr - 2;
-  double m[2][4];
+  const int i0 = side == 0 ? 0 : T.nr - 1;
+  const int i1 = side == 0 ? 1 : T.nr - 2;
+  R f0[NQ], f1[NQ], g0[NQ], g1[NQ];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    int i = s == 0 ? i0 : i1;
-    double fl[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) fl[q] = (double)f[q * plane + (size_t)i * T.nth + j];
-    node_macros(fl, m[s][0], m[s][1], m[s][2], m[s][3]);
+  for (int q = 0; q < NQ; ++q) {
+    f0[q] = f[q * plane + (size_t)i0 * T.nth + j];
+    f1[q] = f[q * plane + (size_t)i1 * T.nth + j];
   }
-  double ct = T.cth[j], st = T.sth[j];
-  double prev[4] = {m[0][0], m[0][1], m[0][2], m[0][3]};
-  double pprev[4] = {m[1][0], m[1][1], m[1][2], m[1][3]};
-  int kind = bc.kind[side];
-  for (int layer = 0; layer < 2; ++layer) {
-    double g[4];
+  ghost_column<R>(T, bc, side, T.cth[j], T.sth[j], f0, f1, g0, g1);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) g[a] = 2.0 * prev[a] - pprev[a];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) { pprev[a] = prev[a]; prev[a] = g[a]; }
-    double rho = g[0], ux = g[1], uy = g[2], E = g[3];
-    if (kind == 0) {                   // WALL: u_r = 0, u_theta = omega r_g
-      double ut = bc.p[side][0] * bc.rg[side][layer];
-      ux = -ut * st;
-      uy = ut * ct;
-    } else if (kind == 1) {            // INFLOW
-      rho = bc.p[side][0];
-      ux = bc.p[side][1] * ct - bc.p[side][2] * st;
-      uy = bc.p[side][1] * st + bc.p[side][2] * ct;
-      E = bc.p[side][3];
-    }                                  // EXTRAPOLATE keeps the extrapolated u
-    EqCoef c;
-    eq_setup(T, rho, ux, uy, E, c);
-    ghost[ghost_index(side, layer, 0, j, T.nth)] = (R)(c.rF[0] * c.A0);
-#pragma unroll
-    for (int k = 1; k <= NK; ++k)
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-        ghost[ghost_index(side, layer, qidx(k, d), j, T.nth)] = (R)eq_val(c, k, d);
+  for (int q = 0; q < NQ; ++q) {
+    ghost[ghost_index(side, 0, q, j, T.nth)] = g0[q];
+    ghost[ghost_index(side, 1, q, j, T.nth)] = g1[q];
   }
 }
 
@@ -83,51 +56,18 @@ __global__ void __launch_bounds__(256) step_node_kernel(Tables T, const R* __res
   const int nr = T.nr, nth = T.nth;
   const size_t plane = (size_t)nr * nth;
   const size_t c0 = (size_t)i * nth + j;
-  R fc[NQ];
-  double fd[NQ];
+  R fc[NQ], res[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) { fc[q] = f[q * plane + c0]; fd[q] = (double)fc[q]; }
-  double rho, ux, uy, E;
-  node_macros(fd, rho, ux, uy, E);
-  EqCoef ec;
-  eq_setup(T, rho, ux, uy, E, ec);
-  const double e = T.e;
-  {
-    double fe = ec.rF[0] * ec.A0;
-    out[c0] = (R)(fe + (fd[0] - fe) * e);     // rest velocity: no convection
-  }
-  const double ct = T.cth[j], st = T.sth[j];
-  const double sr = T.dt_dr, sth = T.dt_dth * T.rinv[i];
-  const int jm1 = j == 0 ? nth - 1 : j - 1, jm2 = jm1 == 0 ? nth - 1 : jm1 - 1;
-  const int jp1 = j == nth - 1 ? 0 : j + 1, jp2 = jp1 == nth - 1 ? 0 : jp1 + 1;
+  for (int q = 0; q < NQ; ++q) fc[q] = f[q * plane + c0];
+  auto row = [&](int q, int di) { return fetch(f, ghost, q, i + di, j, nr, nth, plane); };
+  auto col = [&](int q, int dj) {
+    int t = j + dj;
+    t = t < 0 ? t + nth : (t >= nth ? t - nth : t);
+    return f[q * plane + (size_t)i * nth + t];
+  };
+  node_update<R>(T, i, T.cth[j], T.sth[j], fc, row, col, res);
 #pragma unroll
-  for (int k = 1; k <= NK; ++k) {
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      const int q = qidx(k, d);
-      double fe = eq_val(ec, k, d);
-      double relax = fe + (fd[q] - fe) * e;
-      double vr = vx_q(q) * ct + vy_q(q) * st;
-      double vt = -vx_q(q) * st + vy_q(q) * ct;
-      double Cr = vr * sr, Ct = vt * sth;
-      R u1, u2;
-      if (vr >= 0.0) {
-        u1 = fetch(f, ghost, q, i - 1, j, nr, nth, plane);
-        u2 = fetch(f, ghost, q, i - 2, j, nr, nth, plane);
-      } else {
-        u1 = fetch(f, ghost, q, i + 1, j, nr, nth, plane);
-        u2 = fetch(f, ghost, q, i + 2, j, nr, nth, plane);
-      }
-      double aC = fabs(Cr);
-      R Tr = mwb_term<R>((R)aC, (R)(aC * (1.0 - aC)), fc[q], u1, u2);
-      const R* pl = f + q * plane + (size_t)i * nth;
-      if (vt >= 0.0) { u1 = pl[jm1]; u2 = pl[jm2]; }
-      else           { u1 = pl[jp1]; u2 = pl[jp2]; }
-      aC = fabs(Ct);
-      R Tt = mwb_term<R>((R)aC, (R)(aC * (1.0 - aC)), fc[q], u1, u2);
-      out[q * plane + c0] = (R)relax - Tr - Tt;
-    }
-  }
+  for (int q = 0; q < NQ; ++q) out[q * plane + c0] = res[q];
 }
 
 // ---------------------------------------------------------------------------

@@ -53,28 +53,6 @@ int hip_fail(pclb_ctx* c, hipError_t e, const char* where) {
   return fail(c, PCLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Horner coefficients of F_k(E) for the octagon model: Eqs. F_k with the
-// first row of Table I, B = (B0, B1, B2, B3, B4) = (8, -1/4, 1, -6, 48),
-// suffixes {k+l} = mod{k+l, 4}.  F_k(E) = E (c0 + E (c1 + E (c2 + E c3))) with
-// c0 = B1 e3 / den, c1 = B2 e2 / den, c2 = B3 e1 / den, c3 = B4 / den, where
-// e1, e2, e3 are the elementary symmetric sums of the other three v^2 and
-// den = v_k^2 prod_l (v_k^2 - v_l^2).
-void weight_coefficients(double fc[NK][4]) {
-  const double B1 = -0.25, B2 = 1.0, B3 = -6.0, B4 = 48.0;
-  double x[NK + 1];
-  for (int k = 0; k <= NK; ++k) x[k] = speed(k) * speed(k);
-  for (int k = 1; k <= NK; ++k) {
-    int o[3];
-    for (int l = 1; l <= 3; ++l) o[l - 1] = (k + l <= NK) ? k + l : k + l - NK;
-    double a = x[o[0]], b = x[o[1]], c = x[o[2]];
-    double den = x[k] * (x[k] - a) * (x[k] - b) * (x[k] - c);
-    fc[k - 1][0] = B1 * a * b * c / den;
-    fc[k - 1][1] = B2 * (a * b + b * c + c * a) / den;
-    fc[k - 1][2] = B3 * (a + b + c) / den;
-    fc[k - 1][3] = B4 / den;
-  }
-}
-
 int validate(const pclb_config* c, std::string& why) {
   if (!c) { why = "null config"; return PCLB_EINVAL; }
   if (!(c->r1 > 0.0) || !(c->r2 > c->r1)) { why = "need 0 < r1 < r2"; return PCLB_EINVAL; }
@@ -177,7 +155,6 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   T.dt_dr = cfg->dt / c->dr;
   T.dt_dth = cfg->dt / c->dth;
   T.e = std::exp(-cfg->dt / cfg->tau);
-  weight_coefficients(T.fc);
   T.cth = c->d_geom;
   T.sth = c->d_geom + nth;
   T.rinv = c->d_geom + 2 * nth;

@@ -1,0 +1,93 @@
+// Host emulation of the device step (test infrastructure): runs the shared
+// per-node arithmetic of the HIP kernels (node_update, ghost_column) on the
+// CPU, so that the CPU test-suite can check the device math against the
+// oracle without a GPU.  Loaded by tests/test_device_math.py.
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "../../paper_1302_7104_amd/csrc/common.h"
+
+using namespace pclb;
+
+namespace {
+
+template <class R>
+void run(int nr, int nth, double r1, double r2, double tau, double dt, const int32_t* kind,
+         const double* par, const R* fin, R* fout, int nsteps) {
+  const double PI = 3.14159265358979323846;
+  const double dr = (r2 - r1) / (nr - 1), dth = 2.0 * PI / nth;
+  std::vector<double> cth(nth), sth(nth), rinv(nr), wA(nr);
+  for (int j = 0; j < nth; ++j) {
+    cth[j] = std::cos((j + 1) * dth);
+    sth[j] = std::sin((j + 1) * dth);
+  }
+  for (int i = 0; i < nr; ++i) rinv[i] = 1.0 / (r1 + i * dr);
+  Tables T{};
+  T.nr = nr;
+  T.nth = nth;
+  T.dt_dr = dt / dr;
+  T.dt_dth = dt / dth;
+  T.e = std::exp(-dt / tau);
+  T.cth = cth.data();
+  T.sth = sth.data();
+  T.rinv = rinv.data();
+  T.wA = wA.data();
+  BCdev bc{};
+  for (int s = 0; s < 2; ++s) {
+    bc.kind[s] = kind[s];
+    for (int a = 0; a < 4; ++a) bc.p[s][a] = par[4 * s + a];
+  }
+  bc.rg[0][0] = r1 - dr; bc.rg[0][1] = r1 - 2.0 * dr;
+  bc.rg[1][0] = r2 + dr; bc.rg[1][1] = r2 + 2.0 * dr;
+  const size_t plane = (size_t)nr * nth;
+  std::vector<R> cur(fin, fin + NQ * plane), nxt(NQ * plane), ghost(4 * NQ * (size_t)nth);
+  for (int s = 0; s < nsteps; ++s) {
+    for (int side = 0; side < 2; ++side) {
+      const int i0 = side == 0 ? 0 : nr - 1, i1 = side == 0 ? 1 : nr - 2;
+      for (int j = 0; j < nth; ++j) {
+        R f0[NQ], f1[NQ], g0[NQ], g1[NQ];
+        for (int q = 0; q < NQ; ++q) {
+          f0[q] = cur[q * plane + (size_t)i0 * nth + j];
+          f1[q] = cur[q * plane + (size_t)i1 * nth + j];
+        }
+        ghost_column<R>(T, bc, side, cth[j], sth[j], f0, f1, g0, g1);
+        for (int q = 0; q < NQ; ++q) {
+          ghost[ghost_index(side, 0, q, j, nth)] = g0[q];
+          ghost[ghost_index(side, 1, q, j, nth)] = g1[q];
+        }
+      }
+    }
+    for (int i = 0; i < nr; ++i)
+      for (int j = 0; j < nth; ++j) {
+        R fc[NQ], res[NQ];
+        for (int q = 0; q < NQ; ++q) fc[q] = cur[q * plane + (size_t)i * nth + j];
+        auto row = [&](int q, int di) -> R {
+          const int ii = i + di;
+          if (ii < 0) return ghost[ghost_index(0, -1 - ii, q, j, nth)];
+          if (ii >= nr) return ghost[ghost_index(1, ii - nr, q, j, nth)];
+          return cur[q * plane + (size_t)ii * nth + j];
+        };
+        auto col = [&](int q, int dj) -> R {
+          const int t = ((j + dj) % nth + nth) % nth;
+          return cur[q * plane + (size_t)i * nth + t];
+        };
+        node_update<R>(T, i, cth[j], sth[j], fc, row, col, res);
+        for (int q = 0; q < NQ; ++q) nxt[q * plane + (size_t)i * nth + j] = res[q];
+      }
+    cur.swap(nxt);
+  }
+  for (size_t n = 0; n < cur.size(); ++n) fout[n] = cur[n];
+}
+
+}  // namespace
+
+extern "C" int emu_steps(int32_t nr, int32_t nth, double r1, double r2, double tau, double dt,
+                         const int32_t* kind, const double* par, int32_t precision,
+                         const void* fin, void* fout, int32_t nsteps) {
+  if (precision == 64)
+    run<double>(nr, nth, r1, r2, tau, dt, kind, par, (const double*)fin, (double*)fout, nsteps);
+  else
+    run<float>(nr, nth, r1, r2, tau, dt, kind, par, (const float*)fin, (float*)fout, nsteps);
+  return 0;
+}

@@ -118,16 +118,21 @@ FULL = {"shock_tube": (W.shock_tube, (512, 1024)),
         "kelvin_helmholtz": (W.kelvin_helmholtz, (4096, 8192))}
 
 
+NOISE_ULPS = 32
+
+
 def noise_floor(g, f0, steps, seed=0):
     """How far two FP64 oracle trajectories drift apart when one of them is
-    perturbed by one unit in the last place, at random, after every step: the
-    amplification of rounding-level differences that the problem itself shows."""
+    perturbed at random by NOISE_ULPS units in the last place after every step:
+    the amplification of rounding-level differences that the problem itself
+    shows.  32 ulps stands for the rounding of the equilibrium, whose sums
+    carry a conditioning sum|f|/rho of up to about 16 in these recipes."""
     a, _ = O.step(g, f0, steps)
     b = f0.copy()
     rng = np.random.default_rng(seed)
     for _ in range(steps):
         b, _ = O.step(g, b, 1)
-        b *= 1.0 + 2.0 ** -52 * rng.uniform(-1.0, 1.0, b.shape)
+        b *= 1.0 + NOISE_ULPS * 2.0 ** -52 * rng.uniform(-1.0, 1.0, b.shape)
     return a, rel(b, a)
 
 
@@ -297,7 +302,13 @@ def test_adjoint_step_parity(bc):
         s.adjoint_step(s.state, lam_t, out)
         got = out.double().cpu().numpy()
         assert np.isfinite(got).all()
-        want = O.adjoint_step(g, f0, lam_in)
+        # the derivative branch at near-ties is decided at the precision of the
+        # GPU run on both sides
+        O.set_tie(1e-5 if prec == 32 else 1e-13)
+        try:
+            want = O.adjoint_step(g, f0, lam_in)
+        finally:
+            O.set_tie(1e-13)
         assert rel(got, want) <= tol, (prec, rel(got, want))
 
 
