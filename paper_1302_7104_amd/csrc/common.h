@@ -146,29 +146,54 @@ PCLB_HD inline double eq_val(const EqCoef& c, int k, int d) {
   return c.rF[k] * (c.A0 + w * (c.A1 + w * (c.A2 + w * (c.A3 + w * c.A4))));
 }
 
-// Linear moments of one node: rho, j_x, j_y and eps = sum f v^2 / 2; then the
-// macroscopic u and E = eps / rho - u^2 / 2 (Eqs. moment1-moment3).  The sums
-// are grouped by speed: per group k the plain sum S_k and the projections
-// X_k = sum_d cos(d pi/4) f_kd, Y_k = sum_d sin(d pi/4) f_kd.
-PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double& uy,
-                                   double& E) {
-  double r = f[0], jx = 0.0, jy = 0.0, eps = 0.0;
-#pragma unroll
+// Linear moments of one node, rho, j = sum f v and eps = sum f v^2 (halved at
+// the end), summed per pair of opposite directions (d, d+4), d = 0..3: with
+// sp_k = f_{k,d} + f_{k,d+4} and sm_k = f_{k,d} - f_{k,d+4},
+//   rho_d = sum_k sp_k, j_d = sum_k v_k e_d sm_k, eps_d = sum_k v_k^2 sp_k,
+// the rest velocity counted in rho_0; the four partials are then added in
+// the order d = 0, 1, 2, 3.  Every kernel sums in exactly this order.
+PCLB_HD inline void d4_partial(int d4, double f0, const double* fp, const double* fm, double* P) {
+  double r = f0, jx = 0.0, jy = 0.0, eps = 0.0;
   for (int k = 1; k <= NK; ++k) {
-    const double* g = f + qidx(k, 0);
-    const double S = ((g[0] + g[4]) + (g[2] + g[6])) + ((g[1] + g[5]) + (g[3] + g[7]));
-    const double X = (g[0] - g[4]) + ((g[1] - g[5]) - (g[3] - g[7])) * RSQRT2;
-    const double Y = (g[2] - g[6]) + ((g[1] - g[5]) + (g[3] - g[7])) * RSQRT2;
-    r += S;
-    jx += speed(k) * X;
-    jy += speed(k) * Y;
-    eps += speed(k) * speed(k) * S;
+    const double sp = fp[k - 1] + fm[k - 1];
+    const double sm = fp[k - 1] - fm[k - 1];
+    r += sp;
+    if (cos_d(d4) != 0.0) jx += (speed(k) * cos_d(d4)) * sm;
+    if (sin_d(d4) != 0.0) jy += (speed(k) * sin_d(d4)) * sm;
+    eps += (speed(k) * speed(k)) * sp;
   }
+  P[0] = r;
+  P[1] = jx;
+  P[2] = jy;
+  P[3] = eps;
+}
+
+// rho, u, E (Eqs. moment1-moment3: E = eps / (2 rho) - u^2 / 2) from the four
+// pair partials P[d][0..3].
+PCLB_HD inline void combine_partials(const double P[4][4], double& rho, double& ux, double& uy,
+                                     double& E) {
+  const double r = ((P[0][0] + P[1][0]) + P[2][0]) + P[3][0];
+  const double jx = ((P[0][1] + P[1][1]) + P[2][1]) + P[3][1];
+  const double jy = ((P[0][2] + P[1][2]) + P[2][2]) + P[3][2];
+  const double eps = ((P[0][3] + P[1][3]) + P[2][3]) + P[3][3];
   rho = r;
   const double ir = 1.0 / r;
   ux = jx * ir;
   uy = jy * ir;
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
+}
+
+PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double& uy, double& E) {
+  double P[4][4];
+  for (int d4 = 0; d4 < 4; ++d4) {
+    double fp[NK], fm[NK];
+    for (int k = 1; k <= NK; ++k) {
+      fp[k - 1] = f[qidx(k, d4)];
+      fm[k - 1] = f[qidx(k, d4 + 4)];
+    }
+    d4_partial(d4, d4 == 0 ? f[0] : 0.0, fp, fm, P[d4]);
+  }
+  combine_partials(P, rho, ux, uy, E);
 }
 
 // Relaxed values of the opposite pair (k, d) and (k, d + 4), d = 0..3:

@@ -21,7 +21,6 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int HALO = 2;
 constexpr int OUT_COLS = WAVE - 2 * HALO;     // 60 output columns per strip
-constexpr int WAVES_PER_BLOCK = 4;
 // word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format)
 constexpr int BUF_DWORD3 = 0x00020000;
 
@@ -84,104 +83,163 @@ __device__ inline float lane_from(float v, int byte_addr) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
 }
 
-// One output row i.  For every moving velocity the slots A, B, C hold three
+// Work split: a strip of 64 columns is processed by NSPLIT wavefronts of one
+// workgroup.  Wave W owns the direction pairs d = W*(4/NSPLIT) .. and, for each,
+// the velocities (k, d) and (k, d+4), k = 1..4; wave 0 also owns the rest
+// velocity.  Per row every wave forms the moment partials of its pairs, the
+// partials meet in LDS, and every wave then builds the same equilibrium from
+// their sum and updates its own velocities.
+template <int NSPLIT, int W>
+struct Own {
+  static constexpr int D4N = 4 / NSPLIT;       // direction pairs per wave
+  static constexpr int D40 = W * D4N;          // first pair of this wave
+  static constexpr int NV = 8 * D4N;           // velocities per wave (rest excluded)
+  // local slot v -> velocity: v = (pair * 4 + (k - 1)) * 2 + h
+  static constexpr int q_of(int v) {
+    return qidx(((v >> 1) & 3) + 1, D40 + (v >> 3) + 4 * (v & 1));
+  }
+};
+
+template <int V, int N, class Fn>
+__device__ inline void for_v(Fn&& fn) {
+  if constexpr (V < N) {
+    fn(std::integral_constant<int, V>{});
+    for_v<V + 1, N>(fn);
+  }
+}
+
+// One output row i.  For every owned velocity the slots A, B, C hold three
 // consecutive rows in increasing order: (i-2, i-1, i) when the upwind side is
 // i-1 ("backward"), (i, i+1, i+2) otherwise.  After the velocity's terms are
 // computed, the lowest slot A is refilled with row (lowest + 3), so that the
 // roles rotate A <- B <- C <- A from one row to the next.
-template <bool EDGE>
+template <int NSPLIT, int W, bool EDGE>
 __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G, int i,
-                                 float& r0, float* A, float* B, float* C) {
+                                 float& r0, float* A, float* B, float* C, double* lds) {
+  using O = Own<NSPLIT, W>;
   const unsigned rback = G.rback, tback = G.tback;
-  // moments (Eqs. moment1-3) in double
-  double rho, ux, uy, E;
-  {
-    double fd[NQ];
-    fd[0] = (double)r0;
-    for_q<1>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      constexpr int d = d_of(q);
-      fd[q] = (double)(((rback >> d) & 1u) ? C[q] : A[q]);
-    });
-    node_macros(fd, rho, ux, uy, E);
+  // moment partials of the owned direction pairs
+  double P[4][4];
+#pragma unroll
+  for (int p = 0; p < O::D4N; ++p) {
+    double fp[NK], fm[NK];
+#pragma unroll
+    for (int k = 1; k <= NK; ++k) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int v = (p * 4 + (k - 1)) * 2 + h;
+        const int d = O::D40 + p + 4 * h;
+        const float c = ((rback >> d) & 1u) ? C[v] : A[v];
+        (h ? fm : fp)[k - 1] = (double)c;
+      }
+    }
+    d4_partial(O::D40 + p, (W == 0 && p == 0) ? (double)r0 : 0.0, fp, fm, P[O::D40 + p]);
   }
+  if constexpr (NSPLIT > 1) {
+    // lds[(d * 4 + a) * 64 + lane], double-buffered by row parity
+    double* buf = lds + (i & 1) * (16 * 64);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < O::D4N; ++p)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) buf[((O::D40 + p) * 4 + a) * 64 + lane] = P[O::D40 + p][a];
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      if (d >= O::D40 && d < O::D40 + O::D4N) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) P[d][a] = buf[(d * 4 + a) * 64 + lane];
+    }
+  }
+  double rho, ux, uy, E;
+  combine_partials(P, rho, ux, uy, E);
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
   const float rinv = (float)T.rinv[i];
-  float atr[4];
-#pragma unroll
-  for (int d = 0; d < 4; ++d) atr[d] = G.at[d] * rinv;
   const uint32_t ovoff = (uint32_t)(i * X.nth + X.col) * 4u;
-  // rest velocity: relaxation only
-  {
+  if constexpr (W == 0) {            // rest velocity: relaxation only
     const float res = relax_rest<float>(ec, X.e, X.ome, r0);
     if (X.store) store_f<0>(X, ovoff, res);
     r0 = load_f<EDGE, 0>(X, i + 1);
   }
-  for_q<1>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    constexpr int k = k_of(q), d = d_of(q);
-    if constexpr (d < 4) {
-      constexpr int qm = q + 4;
-      const bool bp = (rback >> d) & 1u, bm = (rback >> (d + 4)) & 1u;
-      const float cp = bp ? C[q] : A[q];
-      const float cm = bm ? C[qm] : A[qm];
-      float rel[2];
-      relax_pair<float>(ec, X.e, X.ome, k, d, cp, cm, rel[0], rel[1]);
-      float aCr, Kr, aCt, Kt;
-      courant<float>((float)speed(k), G.ar[d], aCr, Kr);
-      courant<float>((float)speed(k), atr[d], aCt, Kt);
-      auto one = [&](auto qq, bool back, float c, float rl) {
-        constexpr int Q = decltype(qq)::value;
-        constexpr int D = d_of(Q);
-        const bool tb = (tback >> D) & 1u;
-        const float t1 = lane_from(c, tb ? X.bp_b1 : X.bp_f1);
-        const float t2 = lane_from(c, tb ? X.bp_b2 : X.bp_f2);
-        const float res = mwb_update<float>(rl, c, aCr, Kr, B[Q], back ? A[Q] : C[Q], aCt, Kt, t1, t2);
-        if (X.store) store_f<Q>(X, ovoff, res);
-        A[Q] = load_f<EDGE, Q>(X, back ? i + 1 : i + 3);
-      };
-      one(std::integral_constant<int, q>{}, bp, cp, rel[0]);
-      one(std::integral_constant<int, qm>{}, bm, cm, rel[1]);
-    }
+  for_v<0, O::NV / 2>([&](auto pc) {
+    constexpr int pk = decltype(pc)::value;     // (pair, k) index
+    constexpr int p = pk >> 2, k = (pk & 3) + 1;
+    constexpr int d4 = O::D40 + p;
+    constexpr int vp = pk * 2, vm = pk * 2 + 1;
+    constexpr int qp = qidx(k, d4), qm = qidx(k, d4 + 4);
+    const bool bp = (rback >> d4) & 1u, bm = (rback >> (d4 + 4)) & 1u;
+    const float cp = bp ? C[vp] : A[vp];
+    const float cm = bm ? C[vm] : A[vm];
+    float rel[2];
+    relax_pair<float>(ec, X.e, X.ome, k, d4, cp, cm, rel[0], rel[1]);
+    float aCr, Kr, aCt, Kt;
+    courant<float>((float)speed(k), G.ar[d4], aCr, Kr);
+    courant<float>((float)speed(k), G.at[d4] * rinv, aCt, Kt);
+    auto one = [&](auto vv, auto qq, bool back, float c, float rl) {
+      constexpr int v = decltype(vv)::value;
+      constexpr int q = decltype(qq)::value;
+      constexpr int d = d_of(q);
+      const bool tb = (tback >> d) & 1u;
+      const float t1 = lane_from(c, tb ? X.bp_b1 : X.bp_f1);
+      const float t2 = lane_from(c, tb ? X.bp_b2 : X.bp_f2);
+      const float res = mwb_update<float>(rl, c, aCr, Kr, B[v], back ? A[v] : C[v], aCt, Kt, t1, t2);
+      if (X.store) store_f<q>(X, ovoff, res);
+      A[v] = load_f<EDGE, q>(X, back ? i + 1 : i + 3);
+    };
+    one(std::integral_constant<int, vp>{}, std::integral_constant<int, qp>{}, bp, cp, rel[0]);
+    one(std::integral_constant<int, vm>{}, std::integral_constant<int, qm>{}, bm, cm, rel[1]);
   });
 }
 
-template <bool EDGE>
+template <int NSPLIT, int W, bool EDGE>
 __device__ inline void strip_march(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
-                                   int i_begin, int i_end) {
-  float S0[NQ], S1[NQ], S2[NQ];
-  float r0 = load_f<EDGE, 0>(X, i_begin);
-  for_q<1>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
+                                   int i_begin, int i_end, double* lds) {
+  using O = Own<NSPLIT, W>;
+  float S0[O::NV], S1[O::NV], S2[O::NV];
+  float r0 = 0.0f;
+  if constexpr (W == 0) r0 = load_f<EDGE, 0>(X, i_begin);
+  for_v<0, O::NV>([&](auto vc) {
+    constexpr int v = decltype(vc)::value;
+    constexpr int q = O::q_of(v);
     constexpr int d = d_of(q);
     const int base = ((G.rback >> d) & 1u) ? i_begin - 2 : i_begin;
-    S0[q] = load_f<EDGE, q>(X, base);
-    S1[q] = load_f<EDGE, q>(X, base + 1);
-    S2[q] = load_f<EDGE, q>(X, base + 2);
+    S0[v] = load_f<EDGE, q>(X, base);
+    S1[v] = load_f<EDGE, q>(X, base + 1);
+    S2[v] = load_f<EDGE, q>(X, base + 2);
   });
   for (int i = i_begin; i < i_end; i += 3) {
-    strip_row<EDGE>(T, X, G, i, r0, S0, S1, S2);
+    strip_row<NSPLIT, W, EDGE>(T, X, G, i, r0, S0, S1, S2, lds);
     if (i + 1 >= i_end) break;
-    strip_row<EDGE>(T, X, G, i + 1, r0, S1, S2, S0);
+    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 1, r0, S1, S2, S0, lds);
     if (i + 2 >= i_end) break;
-    strip_row<EDGE>(T, X, G, i + 2, r0, S2, S0, S1);
+    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 2, r0, S2, S0, S1, lds);
   }
+}
+
+template <int NSPLIT, int W>
+__device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
+                                  int i_begin, int i_end, double* lds) {
+  // the chunk reads rows i_begin-2 .. i_end+2 (the last two only as
+  // look-ahead); only chunks next to a wall touch the ghost layers
+  if (i_begin < 2 || i_end + 2 >= X.nr) strip_march<NSPLIT, W, true>(T, X, G, i_begin, i_end, lds);
+  else strip_march<NSPLIT, W, false>(T, X, G, i_begin, i_end, lds);
 }
 
 }  // namespace
 
-__global__ void __launch_bounds__(WAVE * WAVES_PER_BLOCK)
+template <int NSPLIT>
+__global__ void __launch_bounds__(WAVE * NSPLIT)
 step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out,
                   const float* __restrict__ ghost, int chunk_rows, int n_strips) {
+  __shared__ double lds[NSPLIT > 1 ? 2 * 16 * 64 : 1];
   const int lane = threadIdx.x & (WAVE - 1);
-  const int wave = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-  const int strip = wave % n_strips;
-  const int chunk = wave / n_strips;
+  const int w = threadIdx.x >> 6;                     // wave within the group
+  const int strip = blockIdx.x % n_strips;
+  const int chunk = blockIdx.x / n_strips;
   const int nr = T.nr, nth = T.nth;
   const int i_begin = chunk * chunk_rows;
-  if (i_begin >= nr) return;                          // whole wave exits together
-  const int i_end = min(nr, i_begin + chunk_rows);
+  const int i_end = min(nr, i_begin + chunk_rows);    // every block has i_begin < nr
 
   StripCtx X;
   const size_t plane = (size_t)nr * nth;
@@ -209,10 +267,17 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   X.bp_f2 = (lane + 2) << 2;
   DirGeom<float> G;
   dir_geometry(T.cth[X.col], T.sth[X.col], T.dt_dr, T.dt_dth, G);
-  // the chunk reads rows i_begin-2 .. i_end+2 (the last two only as
-  // look-ahead); only chunks next to a wall touch the ghost layers
-  if (i_begin < 2 || i_end + 2 >= nr) strip_march<true>(T, X, G, i_begin, i_end);
-  else strip_march<false>(T, X, G, i_begin, i_end);
+  if constexpr (NSPLIT == 1) {
+    strip_wave<1, 0>(T, X, G, i_begin, i_end, lds);
+  } else if constexpr (NSPLIT == 2) {
+    if (w == 0) strip_wave<2, 0>(T, X, G, i_begin, i_end, lds);
+    else strip_wave<2, 1>(T, X, G, i_begin, i_end, lds);
+  } else {
+    if (w == 0) strip_wave<4, 0>(T, X, G, i_begin, i_end, lds);
+    else if (w == 1) strip_wave<4, 1>(T, X, G, i_begin, i_end, lds);
+    else if (w == 2) strip_wave<4, 2>(T, X, G, i_begin, i_end, lds);
+    else strip_wave<4, 3>(T, X, G, i_begin, i_end, lds);
+  }
 }
 
 template <class R>
@@ -224,30 +289,39 @@ bool strip_supported(const Tables& T) {
 }
 
 int strip_default_chunk(const Tables& T) {
-  // enough (strip, chunk) waves to fill 256 CUs several times over
+  // enough (strip, chunk) workgroups to fill 256 CUs several times over
   const int strips = (T.nth + OUT_COLS - 1) / OUT_COLS;
-  int chunk = 128;
-  while (chunk > 16 && (long)strips * ((T.nr + chunk - 1) / chunk) < 8192) chunk /= 2;
+  int chunk = 32;
+  while (chunk > 8 && (long)strips * ((T.nr + chunk - 1) / chunk) < 4096) chunk /= 2;
   return chunk;
 }
 
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
-                             int chunk_rows, hipStream_t s) {
+                             int chunk_rows, int split, hipStream_t s) {
   if (!strip_supported<R>(T)) return hipErrorNotSupported;
   if (chunk_rows <= 0) chunk_rows = strip_default_chunk(T);
+  if (split <= 0) split = 2;
   const int strips = (T.nth + OUT_COLS - 1) / OUT_COLS;
   const int chunks = (T.nr + chunk_rows - 1) / chunk_rows;
-  const long waves = (long)strips * chunks;
-  const int blocks = (int)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
-  hipLaunchKernelGGL(step_strip_kernel, dim3(blocks), dim3(WAVE * WAVES_PER_BLOCK), 0, s, T,
-                     (const float*)f, (float*)out, (const float*)ghost, chunk_rows, strips);
+  const int blocks = strips * chunks;
+  const float* fi = (const float*)f;
+  float* fo = (float*)out;
+  const float* gh = (const float*)ghost;
+  if (split == 1)
+    hipLaunchKernelGGL(step_strip_kernel<1>, dim3(blocks), dim3(WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips);
+  else if (split == 2)
+    hipLaunchKernelGGL(step_strip_kernel<2>, dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips);
+  else if (split == 4)
+    hipLaunchKernelGGL(step_strip_kernel<4>, dim3(blocks), dim3(4 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template bool strip_supported<float>(const Tables&);
 template bool strip_supported<double>(const Tables&);
-template hipError_t launch_step_strip<float>(const Tables&, const void*, void*, const void*, int, hipStream_t);
-template hipError_t launch_step_strip<double>(const Tables&, const void*, void*, const void*, int, hipStream_t);
+template hipError_t launch_step_strip<float>(const Tables&, const void*, void*, const void*, int, int, hipStream_t);
+template hipError_t launch_step_strip<double>(const Tables&, const void*, void*, const void*, int, int, hipStream_t);
 
 }  // namespace pclb

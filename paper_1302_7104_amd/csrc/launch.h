@@ -14,7 +14,7 @@ template <class R>
 hipError_t launch_step_node(const Tables& T, const void* f, void* out, const void* ghost, hipStream_t s);
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
-                             int chunk_rows, hipStream_t s);
+                             int chunk_rows, int split, hipStream_t s);
 template <class R>
 bool strip_supported(const Tables& T);
 template <class R>
