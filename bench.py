@@ -135,6 +135,64 @@ def cpu_baseline(W, target_s=12.0):
                       f"{dt:.1f} s on {O.num_threads()} OpenMP threads"}
 
 
+def calibrate_copy(torch, gib=1):
+    """A plain device-to-device copy of `gib` GiB, three times: the reference
+    that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def _counter_values(csv_path, counter):
+    """Per-dispatch values of one rocprofv3 counter, listed per kernel name."""
+    import csv
+    from collections import defaultdict
+    per = defaultdict(float)
+    names = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            names[r["Dispatch_Id"]] = r["Kernel_Name"]
+    agg = defaultdict(list)
+    for d, v in per.items():
+        agg[names[d]].append(v)
+    return agg
+
+
+def summarize_counters(fetch_csv, write_csv, nodes, precision=32, copy_gib=1):
+    """Turn the two counter passes into HBM bytes per step-kernel launch.
+    Each counter is scaled by what it reads for the plain copy of known size
+    (copy bytes / counter value), then stored with the kernel source hash."""
+    fetch = _counter_values(fetch_csv, "FETCH_SIZE")
+    write = _counter_values(write_csv, "WRITE_SIZE")
+    copy_bytes = copy_gib * (1 << 30)
+
+    def vals(d, key):
+        return [v for k, vs in d.items() if key in k for v in vs]
+
+    # the copy of known size is the largest copy dispatch; the step kernel is
+    # averaged over its launches
+    f_copy, w_copy = max(vals(fetch, "copyBuffer")), max(vals(write, "copyBuffer"))
+    fs, ws = vals(fetch, "step_strip_kernel"), vals(write, "step_strip_kernel")
+    f_step, w_step = sum(fs) / len(fs), sum(ws) / len(ws)
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    rec = {"source_hash": kernel_source_hash(),
+           f"fp{precision}": {"nodes": nodes, "fetch_bytes": f_step * f_scale,
+                              "write_bytes": w_step * w_scale,
+                              "bytes_per_launch": f_step * f_scale + w_step * w_scale,
+                              "fetch_counter_per_copy_byte": f_copy / copy_bytes,
+                              "write_counter_per_copy_byte": w_copy / copy_bytes,
+                              "algorithmic_bytes": 2 * NQ * nodes * (precision // 8)}}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,7 +201,18 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true", help="headline FP32 step only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/step_kernel_traffic.json from two rocprofv3 --pmc "
+                         "runs (FETCH_SIZE, WRITE_SIZE) of this script and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        rec = summarize_counters(*args.summarize_counters, nodes=4096 * 8192)
+        with open(os.path.join(ROOT, "profiles", "step_kernel_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU execution "
                           "(theta-sector sharding with halo exchange) is not built", "n_gpus": args.gpus}))
@@ -155,6 +224,8 @@ def main():
     from paper_1302_7104_amd.sim import Sim
 
     P, ms, diag = run_forward(W, Sim, torch, 32, args.steps, args.warmup)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     nodes = P.nr * P.nth
     cellvel = NQ * nodes
     value = cellvel / (ms * 1e-3) / 1e9

@@ -23,6 +23,7 @@ constexpr int HALO = 2;
 constexpr int OUT_COLS = WAVE - 2 * HALO;     // 60 output columns per strip
 // word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format)
 constexpr int BUF_DWORD3 = 0x00020000;
+constexpr int NXCD = 8;   // accelerator dies; workgroups are dealt to them round-robin
 
 template <int Q, class Fn>
 __device__ inline void for_q(Fn&& fn) {
@@ -115,7 +116,7 @@ __device__ inline void for_v(Fn&& fn) {
 // roles rotate A <- B <- C <- A from one row to the next.
 template <int NSPLIT, int W, bool EDGE>
 __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G, int i,
-                                 float& r0, float* A, float* B, float* C, double* lds) {
+                                 bool more, float& r0, float* A, float* B, float* C, double* lds) {
   using O = Own<NSPLIT, W>;
   const unsigned rback = G.rback, tback = G.tback;
   // moment partials of the owned direction pairs
@@ -160,7 +161,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   if constexpr (W == 0) {            // rest velocity: relaxation only
     const float res = relax_rest<float>(ec, X.e, X.ome, r0);
     if (X.store) store_f<0>(X, ovoff, res);
-    r0 = load_f<EDGE, 0>(X, i + 1);
+    if (more) r0 = load_f<EDGE, 0>(X, i + 1);
   }
   for_v<0, O::NV / 2>([&](auto pc) {
     constexpr int pk = decltype(pc)::value;     // (pair, k) index
@@ -185,7 +186,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
       const float t2 = lane_from(c, tb ? X.bp_b2 : X.bp_f2);
       const float res = mwb_update<float>(rl, c, aCr, Kr, B[v], back ? A[v] : C[v], aCt, Kt, t1, t2);
       if (X.store) store_f<q>(X, ovoff, res);
-      A[v] = load_f<EDGE, q>(X, back ? i + 1 : i + 3);
+      if (more) A[v] = load_f<EDGE, q>(X, back ? i + 1 : i + 3);
     };
     one(std::integral_constant<int, vp>{}, std::integral_constant<int, qp>{}, bp, cp, rel[0]);
     one(std::integral_constant<int, vm>{}, std::integral_constant<int, qm>{}, bm, cm, rel[1]);
@@ -209,20 +210,20 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
     S2[v] = load_f<EDGE, q>(X, base + 2);
   });
   for (int i = i_begin; i < i_end; i += 3) {
-    strip_row<NSPLIT, W, EDGE>(T, X, G, i, r0, S0, S1, S2, lds);
+    strip_row<NSPLIT, W, EDGE>(T, X, G, i, i + 1 < i_end, r0, S0, S1, S2, lds);
     if (i + 1 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 1, r0, S1, S2, S0, lds);
+    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 1, i + 2 < i_end, r0, S1, S2, S0, lds);
     if (i + 2 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 2, r0, S2, S0, S1, lds);
+    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 2, i + 3 < i_end, r0, S2, S0, S1, lds);
   }
 }
 
 template <int NSPLIT, int W>
 __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                   int i_begin, int i_end, double* lds) {
-  // the chunk reads rows i_begin-2 .. i_end+2 (the last two only as
-  // look-ahead); only chunks next to a wall touch the ghost layers
-  if (i_begin < 2 || i_end + 2 >= X.nr) strip_march<NSPLIT, W, true>(T, X, G, i_begin, i_end, lds);
+  // the chunk reads rows i_begin-2 .. i_end+1; only chunks next to a wall
+  // touch the ghost layers
+  if (i_begin < 2 || i_end + 1 >= X.nr) strip_march<NSPLIT, W, true>(T, X, G, i_begin, i_end, lds);
   else strip_march<NSPLIT, W, false>(T, X, G, i_begin, i_end, lds);
 }
 
@@ -231,12 +232,23 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
 template <int NSPLIT>
 __global__ void __launch_bounds__(WAVE * NSPLIT)
 step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out,
-                  const float* __restrict__ ghost, int chunk_rows, int n_strips) {
+                  const float* __restrict__ ghost, int chunk_rows, int n_strips, int xcd_order) {
   __shared__ double lds[NSPLIT > 1 ? 2 * 16 * 64 : 1];
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x >> 6;                     // wave within the group
-  const int strip = blockIdx.x % n_strips;
-  const int chunk = blockIdx.x / n_strips;
+  // Work item w runs over strips first, then chunks.  With xcd_order the
+  // workgroups dealt to one XCD take a contiguous range of work items, so
+  // that strips next to each other in theta (which read the same cache lines
+  // at their common edge) and the chunks above and below them share that
+  // XCD's L2.
+  int w_item = blockIdx.x;
+  if (xcd_order) {
+    const int nb = gridDim.x, per = nb / NXCD, extra = nb % NXCD;
+    const int x = blockIdx.x % NXCD, local = blockIdx.x / NXCD;
+    w_item = x * per + min(x, extra) + local;
+  }
+  const int strip = w_item % n_strips;
+  const int chunk = w_item / n_strips;
   const int nr = T.nr, nth = T.nth;
   const int i_begin = chunk * chunk_rows;
   const int i_end = min(nr, i_begin + chunk_rows);    // every block has i_begin < nr
@@ -298,10 +310,11 @@ int strip_default_chunk(const Tables& T) {
 
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
-                             int chunk_rows, int split, hipStream_t s) {
+                             const StripTune& tune, hipStream_t s) {
   if (!strip_supported<R>(T)) return hipErrorNotSupported;
-  if (chunk_rows <= 0) chunk_rows = strip_default_chunk(T);
-  if (split <= 0) split = 2;
+  const int chunk_rows = tune.chunk > 0 ? tune.chunk : strip_default_chunk(T);
+  const int split = tune.split > 0 ? tune.split : 2;
+  const int order = tune.order >= 0 ? (tune.order ? 1 : 0) : 1;
   const int strips = (T.nth + OUT_COLS - 1) / OUT_COLS;
   const int chunks = (T.nr + chunk_rows - 1) / chunk_rows;
   const int blocks = strips * chunks;
@@ -309,11 +322,11 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
   float* fo = (float*)out;
   const float* gh = (const float*)ghost;
   if (split == 1)
-    hipLaunchKernelGGL(step_strip_kernel<1>, dim3(blocks), dim3(WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips);
+    hipLaunchKernelGGL(step_strip_kernel<1>, dim3(blocks), dim3(WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips, order);
   else if (split == 2)
-    hipLaunchKernelGGL(step_strip_kernel<2>, dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips);
+    hipLaunchKernelGGL(step_strip_kernel<2>, dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips, order);
   else if (split == 4)
-    hipLaunchKernelGGL(step_strip_kernel<4>, dim3(blocks), dim3(4 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips);
+    hipLaunchKernelGGL(step_strip_kernel<4>, dim3(blocks), dim3(4 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips, order);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -321,7 +334,9 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
 
 template bool strip_supported<float>(const Tables&);
 template bool strip_supported<double>(const Tables&);
-template hipError_t launch_step_strip<float>(const Tables&, const void*, void*, const void*, int, int, hipStream_t);
-template hipError_t launch_step_strip<double>(const Tables&, const void*, void*, const void*, int, int, hipStream_t);
+template hipError_t launch_step_strip<float>(const Tables&, const void*, void*, const void*,
+                                             const StripTune&, hipStream_t);
+template hipError_t launch_step_strip<double>(const Tables&, const void*, void*, const void*,
+                                              const StripTune&, hipStream_t);
 
 }  // namespace pclb

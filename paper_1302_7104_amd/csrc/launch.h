@@ -12,9 +12,16 @@ template <class R>
 hipError_t launch_ghost(const Tables& T, const BCdev& bc, const void* f, void* ghost, hipStream_t s);
 template <class R>
 hipError_t launch_step_node(const Tables& T, const void* f, void* out, const void* ghost, hipStream_t s);
+// Launch shape of the strip kernel; zero fields take the defaults.  None of
+// them changes the results.
+struct StripTune {
+  int chunk = 0;   // rows marched by one workgroup
+  int split = 0;   // wavefronts sharing one strip (1, 2 or 4)
+  int order = -1;  // 1: XCD-contiguous workgroup order, 0: plain order
+};
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
-                             int chunk_rows, int split, hipStream_t s);
+                             const StripTune& tune, hipStream_t s);
 template <class R>
 bool strip_supported(const Tables& T);
 template <class R>

@@ -26,8 +26,7 @@ struct pclb_ctx {
   bool bound = false;
   hipStream_t stream = nullptr;
   int64_t steps = 0;
-  int strip_chunk = 0;          // strip kernel: rows per chunk (0 = automatic)
-  int strip_split = 0;          // strip kernel: wavefronts per strip (0 = automatic)
+  StripTune tune;               // strip kernel launch shape
   // context-owned device memory
   double* d_geom = nullptr;     // cth[nth], sth[nth], rinv[nr], wA[nr]
   void* d_ghost = nullptr;      // 4 * 33 * nth elements of the state type
@@ -88,7 +87,7 @@ hipError_t do_step(pclb_ctx* c, const void* in, void* out) {
   int kern = c->cfg.kernel;
   if (kern == PCLB_KERNEL_STRIP || (kern == PCLB_KERNEL_AUTO && strip_supported<R>(c->T)))
     if (strip_supported<R>(c->T))
-      return launch_step_strip<R>(c->T, in, out, c->d_ghost, c->strip_chunk, c->strip_split, c->stream);
+      return launch_step_strip<R>(c->T, in, out, c->d_ghost, c->tune, c->stream);
   return launch_step_node<R>(c->T, in, out, c->d_ghost, c->stream);
 }
 
@@ -118,8 +117,9 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   if (!c) return fail(nullptr, PCLB_ENOMEM, "host allocation failed");
   c->cfg = *cfg;
   // tuning knobs of the strip kernel (launch shape only; results do not change)
-  if (const char* v = std::getenv("PCLB_STRIP_CHUNK")) c->strip_chunk = std::atoi(v);
-  if (const char* v = std::getenv("PCLB_STRIP_SPLIT")) c->strip_split = std::atoi(v);
+  if (const char* v = std::getenv("PCLB_STRIP_CHUNK")) c->tune.chunk = std::atoi(v);
+  if (const char* v = std::getenv("PCLB_STRIP_SPLIT")) c->tune.split = std::atoi(v);
+  if (const char* v = std::getenv("PCLB_STRIP_ORDER")) c->tune.order = std::atoi(v);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return fail(nullptr, PCLB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
   const int nr = cfg->n_r, nth = cfg->n_theta;
