@@ -208,8 +208,8 @@ template <class T> T mwb_term(double C, const T psi[5], int s_mode) {
 // delta = 0 the term is C delta + C(1-|C|) h, h = (delta - delta') |delta| /
 // (|delta| + |delta'|): dh/d(delta) = dh/d(delta') = 0 when delta' != 0, and
 // (dh/d(delta), dh/d(delta')) = KINK_H when delta' = 0 too.  Elsewhere the
-// derivatives come from forward-mode differentiation of the paper's form
-// (sgn(0) = 0 inside |eta|).
+// derivatives come from forward-mode differentiation of the term in the
+// division-free form of h (sgn(0) = 0 inside |.|).
 double KINK_H[2] = {1.0, 0.0};
 double TIE_EPS = 1e-13;
 
@@ -230,12 +230,16 @@ void mwb_grad(double C, const double psi[5], double g[5]) {
     dd = C + K * h1;
     ddp = K * h2;
   } else {
+    // The term differentiated through the identity
+    //   (1/2)(1 - S(eta))(1 - eta) delta = (delta - delta') |delta| / (|delta| + |delta'|),
+    // the same function written without 1 - S(eta), which cancels to a few
+    // digits when |eta| >> 1 (a difference just above the tie threshold next
+    // to a large one).
     Dual<2> D(delta), Dp(dprime);
     D.d[0] = 1.0;
     Dp.d[1] = 1.0;
-    Dual<2> eta = Dp / D;
-    Dual<2> S = (dabs(eta) - 1.0) / (dabs(eta) + 1.0);
-    Dual<2> t = (C + 0.5 * K * (1.0 - S) * (1.0 - eta)) * D;
+    Dual<2> h = (D - Dp) * dabs(D) / (dabs(D) + dabs(Dp));
+    Dual<2> t = C * D + K * h;
     dd = t.d[0];
     ddp = t.d[1];
   }

@@ -283,6 +283,37 @@ def test_mwb_grad_kinks():
         assert abs(g[n] - want) < 1e-15
 
 
+def test_mwb_grad_large_eta_matches_high_precision():
+    """Where one upwind difference is many orders smaller than the other
+    (|eta| up to 1e9) the derivative still matches the paper's eta-form
+    (Eq. MWB Scheme with S(eta)) differentiated at 50 digits."""
+    import mpmath as mp
+    mp.mp.dps = 50
+
+    def term(C, d, dp):
+        eta = dp / d
+        S = (abs(eta) - 1) / (abs(eta) + 1)
+        return (C + mp.mpf(1) / 2 * C * (1 - abs(C)) * (1 - S) * (1 - eta)) * d
+
+    for C, d, dp in [(0.37, 1e-9, 0.3), (0.81, -2e-11, 0.05), (0.12, 3e-7, -0.2),
+                     (-0.55, 4e-10, -0.7), (-0.2, -1e-8, 0.9)]:
+        Cm, dm, dpm = mp.mpf(C), mp.mpf(d), mp.mpf(dp)
+        dd = float(mp.diff(lambda x: term(Cm, x, dpm), dm))
+        ddp = float(mp.diff(lambda y: term(Cm, dm, y), dpm))
+        # stencil with the given differences on the upwind side
+        c = 0.5
+        if C >= 0:
+            p = np.array([c - d - dp, c - d, c, 0.1, 0.2])
+            want = [-ddp, -dd + ddp, dd, 0, 0]
+        else:
+            p = np.array([0.1, 0.2, c, c + d, c + d + dp])
+            want = [0, 0, -dd, dd - ddp, ddp]
+        # the stencil values are rounded: take the differences they really hold
+        g = O.mwb_grad(C, p)
+        scale = max(abs(x) for x in want)
+        assert max(abs(a - b) for a, b in zip(g, want)) <= 1e-9 * scale, (C, d, dp, g, want)
+
+
 # --------------------------------------------------------------------------
 # Hugoniot helper of the input recipe (Eq. Hugoniot): printed states.
 
