@@ -110,14 +110,20 @@ __host__ __device__ inline size_t ghost_index(int side, int layer, int q, int j,
 //   P(w) = A0 + A1 w + A2 w^2 + A3 w^3 + A4 w^4,
 //   A0 = 1 - a + a^2/2, A1 = g / E, A2 = g / (2E^2), A3 = 1/(6E^3), A4 = 1/(24E^4),
 //   a = u^2 / (2E), g = 1 - a.
+// Moments, equilibrium and relaxation run in double for both state types:
+// the weights have opposite signs at the nearly equal speeds 2.92 and 2.99
+// and P(w) cancels for w against the flow, so that float arithmetic here
+// loses several digits per step (measured: 1e-4 relative after 100 steps),
+// while rounding only the relaxed value to float keeps the FP32 state within
+// about 1e-6 of the FP64 trajectory.
 struct EqCoef {
   double rF[NK + 1];   // rho F_k
   double A0, A1, A2, A3, A4;
   double p[4];         // u . e_d for d = 0..3 (d + 4 is the negative)
 };
 
-PCLB_HD inline void eq_setup(const Tables& T, double rho, double ux, double uy, double E,
-                                EqCoef& c) {
+PCLB_HD inline void eq_setup(const Tables&, double rho, double ux, double uy, double E,
+                             EqCoef& c) {
   double iE = 1.0 / E;
   const double F1 = weight_k<0>(E), F2 = weight_k<1>(E), F3 = weight_k<2>(E), F4 = weight_k<3>(E);
   c.rF[1] = rho * F1;
@@ -183,8 +189,7 @@ PCLB_HD inline void combine_partials(const double P[4][4], double& rho, double& 
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
 }
 
-PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double& uy, double& E) {
-  double P[4][4];
+PCLB_HD inline void node_partials(const double* f, double P[4][4]) {
   for (int d4 = 0; d4 < 4; ++d4) {
     double fp[NK], fm[NK];
     for (int k = 1; k <= NK; ++k) {
@@ -193,35 +198,36 @@ PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double
     }
     d4_partial(d4, d4 == 0 ? f[0] : 0.0, fp, fm, P[d4]);
   }
+}
+
+PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double& uy, double& E) {
+  double P[4][4];
+  node_partials(f, P);
   combine_partials(P, rho, ux, uy, E);
 }
 
 // Relaxed values of the opposite pair (k, d) and (k, d + 4), d = 0..3:
 // f^eq + (f - f^eq) e written as e f + (1 - e) f^eq, with f^eq = rho F_k P(+-w)
-// and P split into its even and odd parts in w.
+// and P split into its even and odd parts in w = v_k pd, pd = u . e_d (the
+// caller passes c.p[d], or its negative to swap the roles of the pair).  In
+// double; the result is rounded once to the state type R.
 template <class R>
-PCLB_HD inline void relax_pair(const EqCoef& c, double e, double one_m_e, int k, int d, R fp, R fm,
-                                  R& rp, R& rm) {
-  const double w = speed(k) * c.p[d];
+PCLB_HD inline void relax_pair(const EqCoef& c, double e, double one_m_e, int k, double pd,
+                               double fp, double fm, R& rp, R& rm) {
+  const double w = speed(k) * pd;
   const double w2 = w * w;
   const double ev = c.A0 + w2 * (c.A2 + w2 * c.A4);
   const double od = w * (c.A1 + w2 * c.A3);
   const double s = one_m_e * c.rF[k];
   const double gp = s * (ev + od), gm = s * (ev - od);
-  if constexpr (sizeof(R) == 8) {
-    rp = fma((double)fp, e, gp);
-    rm = fma((double)fm, e, gm);
-  } else {
-    rp = fmaf(fp, (float)e, (float)gp);
-    rm = fmaf(fm, (float)e, (float)gm);
-  }
+  rp = (R)fma(fp, e, gp);
+  rm = (R)fma(fm, e, gm);
 }
 
 template <class R>
-PCLB_HD inline R relax_rest(const EqCoef& c, double e, double one_m_e, R f0) {
+PCLB_HD inline R relax_rest(const EqCoef& c, double e, double one_m_e, double f0) {
   const double g = one_m_e * (c.rF[0] * c.A0);
-  if constexpr (sizeof(R) == 8) return fma((double)f0, e, g);
-  else return fmaf(f0, (float)e, (float)g);
+  return (R)fma(f0, e, g);
 }
 
 // Direction geometry of one theta column: for each direction d, the sign of
@@ -257,51 +263,47 @@ PCLB_HD inline void courant(R vk, R a, R& aC, R& K) {
 
 // ---------------------------------------------------------------------------
 // MWB convection term (Eq. MWB Scheme) in the division-free form, written with
-// the upwind neighbours u1 (one node upwind) and u2 (two nodes upwind):
-//   T = |C| d1 + |C|(1-|C|) (d1 - d2) |d1| / (|d1| + |d2|),  d1 = c - u1,
-//   d2 = u1 - u2,
+// the upwind differences d1 = c - u1 and d2 = u1 - u2 (u1 one node upwind, u2
+// two nodes upwind):
+//   T = |C| d1 + |C|(1-|C|) (d1 - d2) |d1| / (|d1| + |d2|),
 // which equals [C + C(1-|C|)(1-S(eta))(1-eta)/2] delta for either sign of C,
-// and is 0 in the limiter part when d1 = d2 = 0.
-template <class R> struct Lim;
-template <> struct Lim<double> {
-  PCLB_HD static inline double ratio(double num, double den) {
-    return num / fmax(den, 2.2250738585072014e-308);
-  }
-};
-template <> struct Lim<float> {
-  PCLB_HD static inline float ratio(float num, float den) {
+// and whose limiter part is 0 when d1 = d2 = 0.
+//
+// Limiter part (d1 - d2) |d1| / (|d1| + |d2|).  Double: a guarded IEEE
+// division.  Float on the device: the weight |d1| / (|d1| + |d2|) from the
+// hardware reciprocal, saturated to [0, 1] by the VALU clamp, which also sends
+// the 0 * inf of d1 = d2 = 0 to 0.
+template <class R>
+PCLB_HD inline R mwb_lim(R d1, R d2);
+template <>
+PCLB_HD inline double mwb_lim<double>(double d1, double d2) {
+  const double a1 = fabs(d1), a2 = fabs(d2);
+  return (d1 - d2) * a1 / fmax(a1 + a2, 2.2250738585072014e-308);
+}
+template <>
+PCLB_HD inline float mwb_lim<float>(float d1, float d2) {
+  const float a1 = fabsf(d1), a2 = fabsf(d2);
 #if defined(__HIP_DEVICE_COMPILE__)
-    return num * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f));
+  const float w = __builtin_amdgcn_fmed3f(a1 * __builtin_amdgcn_rcpf(a1 + a2), 0.0f, 1.0f);
 #else
-    return num * (1.0f / fmaxf(den, 1.17549435e-38f));   // host emulation only
+  // host emulation of the device arithmetic (tests only)
+  const float den = a1 + a2;
+  const float w = den == 0.0f ? 0.0f : fminf(a1 * (1.0f / den), 1.0f);
 #endif
-  }
-};
+  return (d1 - d2) * w;
+}
 
 template <class R>
 PCLB_HD inline R mwb_term(R absC, R K, R c, R u1, R u2) {
   const R d1 = c - u1;
   const R d2 = u1 - u2;
-  const R a1 = sizeof(R) == 8 ? (R)fabs((double)d1) : (R)fabsf((float)d1);
-  const R a2 = sizeof(R) == 8 ? (R)fabs((double)d2) : (R)fabsf((float)d2);
-  const R lim = Lim<R>::ratio((d1 - d2) * a1, a1 + a2);
-  return absC * d1 + K * lim;
+  return absC * d1 + K * mwb_lim<R>(d1, d2);
 }
 
-// Limiter part (d1 - d2)|d1| / (|d1| + |d2|) of the MWB term.
+// rel - T_r - T_theta for one velocity from the radial differences (d1r, d2r)
+// with (aCr, Kr) and the azimuthal ones (d1t, d2t) with (aCt, Kt).
 template <class R>
-PCLB_HD inline R mwb_lim(R d1, R d2) {
-  const R a1 = sizeof(R) == 8 ? (R)fabs((double)d1) : (R)fabsf((float)d1);
-  const R a2 = sizeof(R) == 8 ? (R)fabs((double)d2) : (R)fabsf((float)d2);
-  return Lim<R>::ratio((d1 - d2) * a1, a1 + a2);
-}
-
-// rel - T_r - T_theta for one velocity: the radial term from (c, u1r, u2r)
-// with (aCr, Kr), the azimuthal term from (c, u1t, u2t) with (aCt, Kt).
-template <class R>
-PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, R u1t, R u2t) {
-  const R d1r = c - u1r, d2r = u1r - u2r;
-  const R d1t = c - u1t, d2t = u1t - u2t;
+PCLB_HD inline R mwb_update_d(R rel, R aCr, R Kr, R d1r, R d2r, R aCt, R Kt, R d1t, R d2t) {
   const R lr = mwb_lim<R>(d1r, d2r);
   const R lt = mwb_lim<R>(d1t, d2t);
   R res = rel - aCr * d1r;
@@ -309,6 +311,12 @@ PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, 
   res = res - aCt * d1t;
   res = res - Kt * lt;
   return res;
+}
+
+// The same from the centre value c and the upwind neighbours.
+template <class R>
+PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, R u1t, R u2t) {
+  return mwb_update_d<R>(rel, aCr, Kr, c - u1r, u1r - u2r, aCt, Kt, c - u1t, u1t - u2t);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,7 +334,7 @@ PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, co
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
   const double e = T.e, ome = 1.0 - T.e;
-  res[0] = relax_rest<R>(ec, e, ome, fc[0]);       // rest velocity: no convection
+  res[0] = relax_rest<R>(ec, e, ome, fd[0]);       // rest velocity: no convection
   DirGeom<R> G;
   dir_geometry(ct, st, T.dt_dr, T.dt_dth, G);
   const R rinv = (R)T.rinv[i];
@@ -337,7 +345,8 @@ PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, co
 #pragma unroll
     for (int d4 = 0; d4 < 4; ++d4) {
       R rel[2];
-      relax_pair<R>(ec, e, ome, k, d4, fc[qidx(k, d4)], fc[qidx(k, d4 + 4)], rel[0], rel[1]);
+      relax_pair<R>(ec, e, ome, k, ec.p[d4], fd[qidx(k, d4)], fd[qidx(k, d4 + 4)], rel[0],
+                    rel[1]);
       R aCr, Kr, aCt, Kt;
       courant<R>((R)speed(k), G.ar[d4], aCr, Kr);
       courant<R>((R)speed(k), atr[d4], aCt, Kt);

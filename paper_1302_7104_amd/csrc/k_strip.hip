@@ -1,14 +1,24 @@
 // Strip kernel of the combined-scheme step (Eq. combined_scheme) for FP32
-// storage: every wavefront owns a strip of 64 consecutive theta columns and
-// marches in r over a chunk of rows, keeping for each velocity the three
-// values its radial MWB stencil needs (centre and the two upwind neighbours)
-// in registers.  Each f value of the chunk is read from HBM once; the theta
-// neighbours come from the adjacent lanes (ds_bpermute), so only 4 of the 64
-// lanes (2 on each side) are halo columns that produce no output.
+// storage.  A workgroup owns a strip of 64 consecutive theta columns (one per
+// lane) and marches in r over a chunk of rows.  For each velocity a wavefront
+// keeps the three rows its radial MWB stencil needs (centre and the two
+// upwind neighbours) in registers, so every f value of the chunk is read from
+// HBM once.  The azimuthal neighbours come from the adjacent lanes
+// (ds_bpermute); the two lanes at each end of the strip are halo columns that
+// produce no output, so consecutive strips start 60 columns apart.
 //
-// Per row: 33 loads issued one row ahead, moments and equilibrium in double
-// (Eqs. moment1-3, F_k, feq), analytic relaxation (Eq. operator1_new), the
-// radial and azimuthal MWB terms in float, 33 stores.
+// Per row: moments, equilibrium and analytic relaxation in double (Eqs.
+// moment1-3, F_k, feq, operator1_new), the radial and azimuthal MWB terms in
+// float, one store per velocity, the look-ahead loads.
+//
+// Register slots by role.  The radial velocity components of the opposite
+// directions d and d+4 have opposite signs, so on almost every strip one
+// member of each pair is upwind-backward (u1 at row i-1) on all 64 lanes and
+// the other upwind-forward.  A wave on such a strip ("uniform") holds each
+// pair as (backward member, forward member) and picks the planes it reads and
+// writes with scalar offsets, so that its hot loop has no per-lane selects.
+// Strips where a sign changes inside the strip run the same code with lane
+// selects ("mixed").  Both round exactly like the node kernel.
 #include <type_traits>
 
 #include "common.h"
@@ -24,81 +34,25 @@ constexpr int OUT_COLS = WAVE - 2 * HALO;     // 60 output columns per strip
 // word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format)
 constexpr int BUF_DWORD3 = 0x00020000;
 constexpr int NXCD = 8;   // accelerator dies; workgroups are dealt to them round-robin
+// Byte offset beyond the buffers' range: a raw buffer access at this offset
+// is discarded by the hardware range check (a load returns 0).  Used for the
+// halo lanes' stores and the look-ahead loads past a chunk's last row, so that
+// neither needs a branch.
+constexpr uint32_t OOB = 0x80000000u;
 
-template <int Q, class Fn>
-__device__ inline void for_q(Fn&& fn) {
-  if constexpr (Q < NQ) {
-    fn(std::integral_constant<int, Q>{});
-    for_q<Q + 1>(fn);
-  }
-}
-
-// The state is addressed through buffer resources: planes 0..10, 11..21 and
-// 22..32 each from their own base, a plane selected by a scalar offset
-// q' * plane_bytes, the lane's position by a 32-bit vector offset.  Every
-// offset stays below 2^31 (checked by strip_supported).
-constexpr int PLANES_PER_DESC = 11;
-constexpr int NDESC = 3;
-
+// The state is addressed through buffer resources, one per speed k, whose
+// base is plane 8(k-1): velocity (k, d) is plane 1 + d of resource k-1 and
+// the rest velocity plane 0 of resource 0.  A plane is selected by a scalar
+// offset, the lane's position by a 32-bit vector offset; every offset that
+// addresses data stays below 2^31 (checked by strip_supported).
 struct StripCtx {
-  __amdgpu_buffer_rsrc_t fin[NDESC], fout[NDESC], gh;
+  __amdgpu_buffer_rsrc_t fin[NK], fout[NK], gh;
   uint32_t plane_bytes;
   int nr, nth;
-  int col;
-  bool store;
-  double e, ome;
-  int bp_b1, bp_b2, bp_f1, bp_f2;   // ds_bpermute byte addresses of lanes -1, -2, +1, +2
-};
-
-template <int Q>
-__device__ inline uint32_t plane_off(const StripCtx& X) {
-  return (uint32_t)(Q % PLANES_PER_DESC) * X.plane_bytes;
-}
-
-// Value of velocity Q at row `row` of this lane's column: the state for real
-// rows; with EDGE, rows beyond the walls come from the ghost layers (and rows
-// past the last ghost layer, read only after a chunk's last row, are clamped).
-template <bool EDGE, int Q>
-__device__ inline float load_f(const StripCtx& X, int row) {
-  if constexpr (EDGE) {
-    row = min(row, X.nr + 1);
-    if (row < 0 || row >= X.nr) {
-      const int side = row < 0 ? 0 : 1, layer = row < 0 ? -1 - row : row - X.nr;
-      const uint32_t off = (uint32_t)ghost_index(side, layer, Q, X.col, X.nth) * 4u;
-      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(X.gh, off, 0, 0));
-    }
-  }
-  const uint32_t voff = (uint32_t)(row * X.nth + X.col) * 4u;
-  return __uint_as_float(
-      __builtin_amdgcn_raw_buffer_load_b32(X.fin[Q / PLANES_PER_DESC], voff, plane_off<Q>(X), 0));
-}
-
-template <int Q>
-__device__ inline void store_f(const StripCtx& X, uint32_t voff, float v) {
-  // the b32 builtins move raw 32-bit words: pass the float's bits
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), X.fout[Q / PLANES_PER_DESC], voff,
-                                        plane_off<Q>(X), 0);
-}
-
-__device__ inline float lane_from(float v, int byte_addr) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
-}
-
-// Work split: a strip of 64 columns is processed by NSPLIT wavefronts of one
-// workgroup.  Wave W owns the direction pairs d = W*(4/NSPLIT) .. and, for each,
-// the velocities (k, d) and (k, d+4), k = 1..4; wave 0 also owns the rest
-// velocity.  Per row every wave forms the moment partials of its pairs, the
-// partials meet in LDS, and every wave then builds the same equilibrium from
-// their sum and updates its own velocities.
-template <int NSPLIT, int W>
-struct Own {
-  static constexpr int D4N = 4 / NSPLIT;       // direction pairs per wave
-  static constexpr int D40 = W * D4N;          // first pair of this wave
-  static constexpr int NV = 8 * D4N;           // velocities per wave (rest excluded)
-  // local slot v -> velocity: v = (pair * 4 + (k - 1)) * 2 + h
-  static constexpr int q_of(int v) {
-    return qidx(((v >> 1) & 3) + 1, D40 + (v >> 3) + 4 * (v & 1));
-  }
+  int col;                  // this lane's column
+  uint32_t col4;            // its byte offset within a row
+  bool store;               // this lane writes an output (not a halo column)
+  double e, ome;            // exp(-dt/tau) and 1 - exp(-dt/tau)
 };
 
 template <int V, int N, class Fn>
@@ -109,41 +63,105 @@ __device__ inline void for_v(Fn&& fn) {
   }
 }
 
+__device__ inline float lane_from(float v, int byte_addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
+}
+
+// Work split: a strip is processed by NSPLIT wavefronts of one workgroup.
+// Wave W owns the direction pairs d4 = D40 .. D40 + D4N - 1 and, for each,
+// the velocities (k, d4) and (k, d4 + 4), k = 1..4; wave 0 also owns the rest
+// velocity.  Per row every wave forms the moment partials of its pairs, the
+// partials meet in LDS, and every wave then builds the same equilibrium from
+// their sum and updates its own velocities.
+template <int NSPLIT, int W>
+struct Own {
+  static constexpr int D4N = 4 / NSPLIT;       // direction pairs per wave
+  static constexpr int D40 = W * D4N;          // first pair of this wave
+  static constexpr int NV = 8 * D4N;           // velocities per wave (rest excluded)
+  // slot v = (pl * 4 + (k - 1)) * 2 + h: pair d4 = D40 + pl, speed k, member h
+  static constexpr int pl_of(int v) { return v >> 3; }
+  static constexpr int k_of_v(int v) { return ((v >> 1) & 3) + 1; }
+  static constexpr int h_of(int v) { return v & 1; }
+};
+
+// Per-wave role table.  Member h of pair pl is direction d4 + 4 (h ^ swap):
+// in a uniform wave member 0 is the backward one on every lane; in a mixed
+// wave swap = 0 and the roles are per lane.
+template <int D4N>
+struct Roles {
+  uint32_t soff[D4N][2];    // byte offset of member h's plane within its resource
+  int qb[D4N][2];           // 1 + direction of member h (its plane within the resource)
+  double sg[D4N];           // +1, or -1 when the members are swapped
+};
+
+// Load of a slot's velocity (speed K, plane qb of resource K-1) at row `row`;
+// voff is the byte offset of this lane's column in that row (or OOB).  With
+// EDGE, rows beyond the walls come from the ghost layers.
+template <bool EDGE, int K>
+__device__ inline float load_slot(const StripCtx& X, uint32_t soff, int qb, int row, uint32_t voff,
+                                  bool on) {
+  if constexpr (EDGE) {
+    if (row < 0 || row >= X.nr) {
+      const int side = row < 0 ? 0 : 1, layer = row < 0 ? -1 - row : row - X.nr;
+      const int q = qb + ND * (K - 1);
+      const uint32_t off = on ? (uint32_t)ghost_index(side, layer, q, X.col, X.nth) * 4u : OOB;
+      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(X.gh, off, 0, 0));
+    }
+  }
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(X.fin[K - 1], voff, soff, 0));
+}
+
+template <int K>
+__device__ inline void store_slot(const StripCtx& X, uint32_t soff, uint32_t voff, float v) {
+  // the b32 builtins move raw 32-bit words: pass the float's bits
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), X.fout[K - 1], voff, soff, 0);
+}
+
+__device__ inline uint32_t row_off(const StripCtx& X, int row, bool on) {
+  return on ? (uint32_t)(row * X.nth) * 4u + X.col4 : OOB;
+}
+
 // One output row i.  For every owned velocity the slots A, B, C hold three
 // consecutive rows in increasing order: (i-2, i-1, i) when the upwind side is
 // i-1 ("backward"), (i, i+1, i+2) otherwise.  After the velocity's terms are
 // computed, the lowest slot A is refilled with row (lowest + 3), so that the
 // roles rotate A <- B <- C <- A from one row to the next.
-template <int NSPLIT, int W, bool EDGE>
-__device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G, int i,
-                                 bool more, float& r0, float* A, float* B, float* C, double* lds) {
+template <int NSPLIT, int W, bool EDGE, bool UNI>
+__device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
+                                 const Roles<4 / NSPLIT>& RL, int i, bool more, const int* ta,
+                                 float& r0, float* A, float* B, float* C, double* lds) {
   using O = Own<NSPLIT, W>;
-  const unsigned rback = G.rback, tback = G.tback;
+  const int lane = threadIdx.x & 63;
+  // backward role of slot v: fixed in a uniform wave, per lane otherwise
+  auto back = [&](int v) -> bool {
+    if constexpr (UNI) return O::h_of(v) == 0;
+    else return (G.rback >> (O::D40 + O::pl_of(v) + 4 * O::h_of(v))) & 1u;
+  };
   // moment partials of the owned direction pairs
   double P[4][4];
 #pragma unroll
-  for (int p = 0; p < O::D4N; ++p) {
-    double fp[NK], fm[NK];
+  for (int pl = 0; pl < O::D4N; ++pl) {
+    double f0[NK], f1[NK];
 #pragma unroll
     for (int k = 1; k <= NK; ++k) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int v = (p * 4 + (k - 1)) * 2 + h;
-        const int d = O::D40 + p + 4 * h;
-        const float c = ((rback >> d) & 1u) ? C[v] : A[v];
-        (h ? fm : fp)[k - 1] = (double)c;
-      }
+      const int v0 = (pl * 4 + (k - 1)) * 2, v1 = v0 + 1;
+      f0[k - 1] = (double)(back(v0) ? C[v0] : A[v0]);
+      f1[k - 1] = (double)(back(v1) ? C[v1] : A[v1]);
     }
-    d4_partial(O::D40 + p, (W == 0 && p == 0) ? (double)r0 : 0.0, fp, fm, P[O::D40 + p]);
+    double* Pd = P[O::D40 + pl];
+    d4_partial(O::D40 + pl, (W == 0 && pl == 0) ? (double)r0 : 0.0, f0, f1, Pd);
+    if constexpr (UNI) {            // f0 - f1 was taken with the members swapped
+      Pd[1] *= RL.sg[pl];
+      Pd[2] *= RL.sg[pl];
+    }
   }
   if constexpr (NSPLIT > 1) {
     // lds[(d * 4 + a) * 64 + lane], double-buffered by row parity
     double* buf = lds + (i & 1) * (16 * 64);
-    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int p = 0; p < O::D4N; ++p)
+    for (int pl = 0; pl < O::D4N; ++pl)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) buf[((O::D40 + p) * 4 + a) * 64 + lane] = P[O::D40 + p][a];
+      for (int a = 0; a < 4; ++a) buf[((O::D40 + pl) * 4 + a) * 64 + lane] = P[O::D40 + pl][a];
     __syncthreads();
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -157,74 +175,131 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
   const float rinv = (float)T.rinv[i];
-  const uint32_t ovoff = (uint32_t)(i * X.nth + X.col) * 4u;
+  const uint32_t ovoff = X.store ? (uint32_t)(i * X.nth) * 4u + X.col4 : OOB;
+  const uint32_t vb = row_off(X, i + 1, more), vf = row_off(X, i + 3, more);
   if constexpr (W == 0) {            // rest velocity: relaxation only
-    const float res = relax_rest<float>(ec, X.e, X.ome, r0);
-    if (X.store) store_f<0>(X, ovoff, res);
-    if (more) r0 = load_f<EDGE, 0>(X, i + 1);
+    const float res = relax_rest<float>(ec, X.e, X.ome, (double)r0);
+    store_slot<1>(X, 0, ovoff, res);
+    r0 = load_slot<EDGE, 1>(X, 0, 0, i + 1, vb, more);
   }
   for_v<0, O::NV / 2>([&](auto pc) {
     constexpr int pk = decltype(pc)::value;     // (pair, k) index
-    constexpr int p = pk >> 2, k = (pk & 3) + 1;
-    constexpr int d4 = O::D40 + p;
-    constexpr int vp = pk * 2, vm = pk * 2 + 1;
-    constexpr int qp = qidx(k, d4), qm = qidx(k, d4 + 4);
-    const bool bp = (rback >> d4) & 1u, bm = (rback >> (d4 + 4)) & 1u;
-    const float cp = bp ? C[vp] : A[vp];
-    const float cm = bm ? C[vm] : A[vm];
+    constexpr int pl = pk >> 2, k = (pk & 3) + 1;
+    constexpr int d4 = O::D40 + pl;
+    constexpr int v0 = pk * 2, v1 = pk * 2 + 1;
+    const bool b0 = back(v0), b1 = back(v1);
+    const float c0 = b0 ? C[v0] : A[v0];
+    const float c1 = b1 ? C[v1] : A[v1];
     float rel[2];
-    relax_pair<float>(ec, X.e, X.ome, k, d4, cp, cm, rel[0], rel[1]);
+    const double pd = UNI ? RL.sg[pl] * ec.p[d4] : ec.p[d4];
+    relax_pair<float>(ec, X.e, X.ome, k, pd, (double)c0, (double)c1, rel[0], rel[1]);
     float aCr, Kr, aCt, Kt;
     courant<float>((float)speed(k), G.ar[d4], aCr, Kr);
     courant<float>((float)speed(k), G.at[d4] * rinv, aCt, Kt);
-    auto one = [&](auto vv, auto qq, bool back, float c, float rl) {
+    auto one = [&](auto vv, bool bk, float c, float rl) {
       constexpr int v = decltype(vv)::value;
-      constexpr int q = decltype(qq)::value;
-      constexpr int d = d_of(q);
-      const bool tb = (tback >> d) & 1u;
-      const float t1 = lane_from(c, tb ? X.bp_b1 : X.bp_f1);
-      const float t2 = lane_from(c, tb ? X.bp_b2 : X.bp_f2);
-      const float res = mwb_update<float>(rl, c, aCr, Kr, B[v], back ? A[v] : C[v], aCt, Kt, t1, t2);
-      if (X.store) store_f<q>(X, ovoff, res);
-      if (more) A[v] = load_f<EDGE, q>(X, back ? i + 1 : i + 3);
+      constexpr int h = O::h_of(v);
+      // azimuthal differences: d1 from the upwind lane; d2 is that lane's d1
+      // where every lane has the same upwind side (uniform waves), else it is
+      // formed from the value two lanes upwind
+      const float u1t = lane_from(c, ta[v]);
+      const float d1t = c - u1t;
+      float d2t;
+      if constexpr (UNI) d2t = lane_from(d1t, ta[v]);
+      else d2t = u1t - lane_from(c, (ta[v] << 1) - (lane << 2));
+      const float u1r = B[v];
+      const float d1r = c - u1r, d2r = u1r - (bk ? A[v] : C[v]);
+      const float res = mwb_update_d<float>(rl, aCr, Kr, d1r, d2r, aCt, Kt, d1t, d2t);
+      store_slot<k>(X, RL.soff[pl][h], ovoff, res);
+      A[v] = load_slot<EDGE, k>(X, RL.soff[pl][h], RL.qb[pl][h], bk ? i + 1 : i + 3, bk ? vb : vf,
+                                more);
     };
-    one(std::integral_constant<int, vp>{}, std::integral_constant<int, qp>{}, bp, cp, rel[0]);
-    one(std::integral_constant<int, vm>{}, std::integral_constant<int, qm>{}, bm, cm, rel[1]);
+    one(std::integral_constant<int, v0>{}, b0, c0, rel[0]);
+    one(std::integral_constant<int, v1>{}, b1, c1, rel[1]);
   });
 }
 
-template <int NSPLIT, int W, bool EDGE>
+template <int NSPLIT, int W, bool EDGE, bool UNI>
 __device__ inline void strip_march(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
-                                   int i_begin, int i_end, double* lds) {
+                                   const Roles<4 / NSPLIT>& RL, int i_begin, int i_end,
+                                   double* lds) {
   using O = Own<NSPLIT, W>;
   float S0[O::NV], S1[O::NV], S2[O::NV];
+  // ds_bpermute byte address of the azimuthally upwind lane, per slot
+  int ta[O::NV];
+  const int lane = threadIdx.x & (WAVE - 1);
   float r0 = 0.0f;
-  if constexpr (W == 0) r0 = load_f<EDGE, 0>(X, i_begin);
+  if constexpr (W == 0) r0 = load_slot<EDGE, 1>(X, 0, 0, i_begin, row_off(X, i_begin, true), true);
   for_v<0, O::NV>([&](auto vc) {
     constexpr int v = decltype(vc)::value;
-    constexpr int q = O::q_of(v);
-    constexpr int d = d_of(q);
-    const int base = ((G.rback >> d) & 1u) ? i_begin - 2 : i_begin;
-    S0[v] = load_f<EDGE, q>(X, base);
-    S1[v] = load_f<EDGE, q>(X, base + 1);
-    S2[v] = load_f<EDGE, q>(X, base + 2);
+    constexpr int pl = O::pl_of(v), h = O::h_of(v), k = O::k_of_v(v);
+    const int qb = RL.qb[pl][h];
+    const int d = qb - 1;                       // direction of the slot's velocity
+    ta[v] = (((G.tback >> d) & 1u) ? lane - 1 : lane + 1) << 2;
+    const bool bk = UNI ? h == 0 : ((G.rback >> d) & 1u);
+    const int base = bk ? i_begin - 2 : i_begin;
+    const uint32_t so = RL.soff[pl][h];
+    S0[v] = load_slot<EDGE, k>(X, so, qb, base, row_off(X, base, true), true);
+    S1[v] = load_slot<EDGE, k>(X, so, qb, base + 1, row_off(X, base + 1, true), true);
+    S2[v] = load_slot<EDGE, k>(X, so, qb, base + 2, row_off(X, base + 2, true), true);
   });
   for (int i = i_begin; i < i_end; i += 3) {
-    strip_row<NSPLIT, W, EDGE>(T, X, G, i, i + 1 < i_end, r0, S0, S1, S2, lds);
+    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i, i + 1 < i_end, ta, r0, S0, S1, S2, lds);
     if (i + 1 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 1, i + 2 < i_end, r0, S1, S2, S0, lds);
+    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 1, i + 2 < i_end, ta, r0, S1, S2, S0, lds);
     if (i + 2 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE>(T, X, G, i + 2, i + 3 < i_end, r0, S2, S0, S1, lds);
+    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 2, i + 3 < i_end, ta, r0, S2, S0, S1, lds);
   }
 }
 
 template <int NSPLIT, int W>
 __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                   int i_begin, int i_end, double* lds) {
+  using O = Own<NSPLIT, W>;
+  // Roles of the owned pairs: uniform when, on every lane of the wave, exactly
+  // one member of each pair is radially backward, the same member on all
+  // lanes, and each member has the same azimuthal upwind side on all lanes.
+  Roles<O::D4N> RL;
+  bool uni = true;
+#pragma unroll
+  for (int pl = 0; pl < O::D4N; ++pl) {
+    const int d4 = O::D40 + pl;
+    const uint64_t all = ~0ull;
+    const uint64_t b0 = __ballot((G.rback >> d4) & 1u);
+    const uint64_t b1 = __ballot((G.rback >> (d4 + 4)) & 1u);
+    const uint64_t t0 = __ballot((G.tback >> d4) & 1u);
+    const uint64_t t1 = __ballot((G.tback >> (d4 + 4)) & 1u);
+    const bool swap = b0 == 0 && b1 == all;
+    uni = uni && ((b0 == all && b1 == 0) || swap) && (t0 == 0 || t0 == all) &&
+          (t1 == 0 || t1 == all);
+    RL.sg[pl] = swap ? -1.0 : 1.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int qb = 1 + d4 + 4 * (h ^ (swap ? 1 : 0));
+      RL.qb[pl][h] = qb;
+      RL.soff[pl][h] = (uint32_t)qb * X.plane_bytes;
+    }
+  }
   // the chunk reads rows i_begin-2 .. i_end+1; only chunks next to a wall
   // touch the ghost layers
-  if (i_begin < 2 || i_end + 1 >= X.nr) strip_march<NSPLIT, W, true>(T, X, G, i_begin, i_end, lds);
-  else strip_march<NSPLIT, W, false>(T, X, G, i_begin, i_end, lds);
+  const bool edge = i_begin < 2 || i_end + 1 >= X.nr;
+  if (uni) {
+    if (edge) strip_march<NSPLIT, W, true, true>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, true>(T, X, G, RL, i_begin, i_end, lds);
+  } else {
+#pragma unroll
+    for (int pl = 0; pl < O::D4N; ++pl) {       // mixed: members in natural order
+      RL.sg[pl] = 1.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int qb = 1 + O::D40 + pl + 4 * h;
+        RL.qb[pl][h] = qb;
+        RL.soff[pl][h] = (uint32_t)qb * X.plane_bytes;
+      }
+    }
+    if (edge) strip_march<NSPLIT, W, true, false>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, false>(T, X, G, RL, i_begin, i_end, lds);
+  }
 }
 
 }  // namespace
@@ -257,11 +332,11 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   const size_t plane = (size_t)nr * nth;
   X.plane_bytes = (uint32_t)(plane * 4);
 #pragma unroll
-  for (int b = 0; b < NDESC; ++b) {
-    X.fin[b] = __builtin_amdgcn_make_buffer_rsrc((void*)(f + b * PLANES_PER_DESC * plane), 0,
-                                                 0x7fffffff, BUF_DWORD3);
-    X.fout[b] = __builtin_amdgcn_make_buffer_rsrc((void*)(out + b * PLANES_PER_DESC * plane), 0,
-                                                  0x7fffffff, BUF_DWORD3);
+  for (int k = 1; k <= NK; ++k) {
+    X.fin[k - 1] = __builtin_amdgcn_make_buffer_rsrc((void*)(f + ND * (k - 1) * plane), 0,
+                                                     0x7fffffff, BUF_DWORD3);
+    X.fout[k - 1] = __builtin_amdgcn_make_buffer_rsrc((void*)(out + ND * (k - 1) * plane), 0,
+                                                      0x7fffffff, BUF_DWORD3);
   }
   X.gh = __builtin_amdgcn_make_buffer_rsrc((void*)ghost, 0, 0x7fffffff, BUF_DWORD3);
   X.nr = nr;
@@ -270,13 +345,10 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   const int jout = strip * OUT_COLS + lane - HALO;     // may be -2 .. nth+1
   int col = jout % nth;
   X.col = col < 0 ? col + nth : col;
+  X.col4 = (uint32_t)X.col * 4u;
   X.store = lane >= HALO && lane < WAVE - HALO && jout < nth;
   X.e = T.e;
   X.ome = 1.0 - T.e;
-  X.bp_b1 = (lane - 1) << 2;
-  X.bp_b2 = (lane - 2) << 2;
-  X.bp_f1 = (lane + 1) << 2;
-  X.bp_f2 = (lane + 2) << 2;
   DirGeom<float> G;
   dir_geometry(T.cth[X.col], T.sth[X.col], T.dt_dr, T.dt_dth, G);
   if constexpr (NSPLIT == 1) {
@@ -294,10 +366,11 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
 
 template <class R>
 bool strip_supported(const Tables& T) {
-  // every buffer offset (10 planes + the lane offset) must stay below 2^31
+  // every offset that addresses data (at most 8 planes past a resource base,
+  // plus the lane offset, kept below 9 planes) must stay below 2^31, the OOB
+  // marker; the lanes of one strip must be distinct columns
   const double plane_bytes = 4.0 * T.nr * (double)T.nth;
-  return std::is_same<R, float>::value && T.nth >= WAVE &&
-         (double)PLANES_PER_DESC * plane_bytes < 2147483647.0;
+  return std::is_same<R, float>::value && T.nth >= WAVE && 9.0 * plane_bytes < 2147483647.0;
 }
 
 int strip_default_chunk(const Tables& T) {
@@ -322,11 +395,14 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
   float* fo = (float*)out;
   const float* gh = (const float*)ghost;
   if (split == 1)
-    hipLaunchKernelGGL(step_strip_kernel<1>, dim3(blocks), dim3(WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips, order);
+    hipLaunchKernelGGL(step_strip_kernel<1>, dim3(blocks), dim3(WAVE), 0, s, T, fi, fo, gh,
+                       chunk_rows, strips, order);
   else if (split == 2)
-    hipLaunchKernelGGL(step_strip_kernel<2>, dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips, order);
+    hipLaunchKernelGGL(step_strip_kernel<2>, dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo, gh,
+                       chunk_rows, strips, order);
   else if (split == 4)
-    hipLaunchKernelGGL(step_strip_kernel<4>, dim3(blocks), dim3(4 * WAVE), 0, s, T, fi, fo, gh, chunk_rows, strips, order);
+    hipLaunchKernelGGL(step_strip_kernel<4>, dim3(blocks), dim3(4 * WAVE), 0, s, T, fi, fo, gh,
+                       chunk_rows, strips, order);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

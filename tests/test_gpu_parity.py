@@ -291,25 +291,44 @@ def test_fields_match_oracle():
 
 @pytest.mark.parametrize("bc", BCS)
 def test_adjoint_step_parity(bc):
+    """One adjoint step on a noisy smooth state, both sides given the same
+    state (the oracle's, rounded to the run's precision on the host).
+
+    The MWB switch is not differentiable where an upwind difference vanishes;
+    both sides count a difference within a tie threshold (1e-13 FP64, 1e-5
+    FP32, relative to the stencil) as zero.  Entries whose oracle value moves
+    when that threshold moves by 1% sit at such a branch point: there either
+    branch is a valid one-sided derivative, and the GPU value must equal one
+    of the two.  All other entries are compared as a whole."""
     P, F = smooth_problem(21, 70, bc, 12)
     g = grid_of(P)
     for prec, tol in ((64, 1e-12), (32, 1e-5), (64, 1e-12), (32, 1e-5)):
-        s, f0 = start(P, F, prec, noise_seed=13, amp=1e-2)
+        s, f_or = start(P, F, prec, noise_seed=13, amp=1e-2)
+        f_in = f_or.astype(np.float32).astype(np.float64) if prec == 32 else f_or
+        s.load_state(torch.as_tensor(f_in, dtype=s.dtype, device=s.device))
         lam = W.noise((33, P.nr, P.nth), 1.0, 14)
         lam_in = lam.astype(np.float32).astype(np.float64) if prec == 32 else lam
-        lam_t = torch.as_tensor(lam, dtype=s.dtype, device=s.device).contiguous()
+        lam_t = torch.as_tensor(lam_in, dtype=s.dtype, device=s.device).contiguous()
         out = torch.full_like(lam_t, float("nan"))    # unwritten entries stay NaN
         s.adjoint_step(s.state, lam_t, out)
         got = out.double().cpu().numpy()
         assert np.isfinite(got).all()
-        # the derivative branch at near-ties is decided at the precision of the
-        # GPU run on both sides
-        O.set_tie(1e-5 if prec == 32 else 1e-13)
+        tie = 1e-5 if prec == 32 else 1e-13
+        want = {}
         try:
-            want = O.adjoint_step(g, f0, lam_in)
+            for t in (tie, 0.99 * tie, 1.01 * tie):
+                O.set_tie(t)
+                want[t] = O.adjoint_step(g, f_in, lam_in)
         finally:
             O.set_tie(1e-13)
-        assert rel(got, want) <= tol, (prec, rel(got, want))
+        w0, wlo, whi = want[tie], want[0.99 * tie], want[1.01 * tie]
+        scale = np.abs(w0).max()
+        branch = np.abs(wlo - whi) > 1e-9 * scale
+        assert branch.sum() <= 1e-3 * branch.size, branch.sum()
+        unique = ~branch
+        assert rel(got[unique], w0[unique]) <= tol, (prec, rel(got[unique], w0[unique]))
+        near = np.minimum(np.abs(got - wlo), np.abs(got - whi))[branch]
+        assert (near <= 1e3 * tol * scale).all(), (prec, near.max() / scale)
 
 
 def test_adjoint_init_parity():
