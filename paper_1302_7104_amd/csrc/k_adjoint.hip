@@ -11,124 +11,11 @@
 // kernels keep their working set in registers (no private scratch memory).
 #include <type_traits>
 
+#include "adjoint.h"
 #include "common.h"
 #include "launch.h"
 
 namespace pclb {
-
-// Jacobian of the equilibrium (Eq. feq) with respect to (rho, u_x, u_y, E)
-// at one state, applied to cotangents one velocity at a time.
-struct FeqJac {
-  EqCoef c;
-  double rho, ux, uy;
-  double F[NK + 1], Fp[NK + 1];              // F_k(E) and dF_k/dE
-  double A0u, A1u, A2u;                      // dA_n / d(u^2)
-  double A0E, A1E, A2E, A3E, A4E;            // dA_n / dE
-};
-
-__device__ inline void feq_jac_setup(const Tables& T, double rho, double ux, double uy, double E,
-                                     FeqJac& J) {
-  eq_setup(T, rho, ux, uy, E, J.c);
-  J.rho = rho;
-  J.ux = ux;
-  J.uy = uy;
-  J.F[1] = weight_k<0>(E); J.F[2] = weight_k<1>(E); J.F[3] = weight_k<2>(E); J.F[4] = weight_k<3>(E);
-  J.Fp[1] = weight_k_prime<0>(E); J.Fp[2] = weight_k_prime<1>(E);
-  J.Fp[3] = weight_k_prime<2>(E); J.Fp[4] = weight_k_prime<3>(E);
-  J.F[0] = 1.0 - 8.0 * (((J.F[1] + J.F[2]) + J.F[3]) + J.F[4]);
-  J.Fp[0] = -8.0 * (((J.Fp[1] + J.Fp[2]) + J.Fp[3]) + J.Fp[4]);
-  const double iE = 1.0 / E, iE2 = iE * iE, iE3 = iE2 * iE;
-  const double a = 0.5 * (ux * ux + uy * uy) * iE, g = 1.0 - a;
-  J.A0u = -0.5 * g * iE;
-  J.A1u = -0.5 * iE2;
-  J.A2u = -0.25 * iE3;
-  J.A0E = a * g * iE;
-  J.A1E = (2.0 * a - 1.0) * iE2;
-  J.A2E = 0.5 * (a - 2.0 * g) * iE3;
-  J.A3E = -0.5 * iE2 * iE2;
-  J.A4E = -(1.0 / 6.0) * iE2 * iE3;
-}
-
-// G += l * d f^eq_q / d(rho, u_x, u_y, E) for velocity q = (k, d).
-template <int Q>
-__device__ inline void feq_jac_accum(const FeqJac& J, double l, double G[4]) {
-  constexpr int k = k_of(Q), d = d_of(Q);
-  double w;
-  if (Q == 0) w = 0.0;
-  else w = speed(k) * (d < 4 ? J.c.p[d & 3] : -J.c.p[d & 3]);
-  const EqCoef& c = J.c;
-  const double P = c.A0 + w * (c.A1 + w * (c.A2 + w * (c.A3 + w * c.A4)));
-  const double Pw = c.A1 + w * (2.0 * c.A2 + w * (3.0 * c.A3 + w * 4.0 * c.A4));
-  const double Pu = J.A0u + w * (J.A1u + w * J.A2u);
-  const double PE = J.A0E + w * (J.A1E + w * (J.A2E + w * (J.A3E + w * J.A4E)));
-  const double rFk = J.rho * J.F[k];
-  G[0] += l * J.F[k] * P;
-  G[1] += l * rFk * (Pw * vx_q(Q) + Pu * 2.0 * J.ux);
-  G[2] += l * rFk * (Pw * vy_q(Q) + Pu * 2.0 * J.uy);
-  G[3] += l * J.rho * (J.Fp[k] * P + J.F[k] * PE);
-}
-
-// (G_rho, G_ux, G_uy, G_E) -> cotangents of M = (rho, j_x, j_y, eps) through
-// u = j / rho, E = eps / rho - u^2 / 2.
-__device__ inline void to_moment_cotangent(double rho, double ux, double uy, double E,
-                                           const double G[4], double gM[4]) {
-  const double ir = 1.0 / rho;
-  gM[0] = G[0] - (G[1] * ux + G[2] * uy) * ir + G[3] * (0.5 * (ux * ux + uy * uy) - E) * ir;
-  gM[1] = (G[1] - G[3] * ux) * ir;
-  gM[2] = (G[2] - G[3] * uy) * ir;
-  gM[3] = G[3] * ir;
-}
-
-// Derivatives of T = |C| d1 + K h(d1, d2), d1 = c - u1, d2 = u1 - u2,
-// h = (d1 - d2)|d1| / (|d1| + |d2|), with respect to (c, u1, u2).  T is not
-// differentiable where d1 or d2 vanishes; a difference within `eps` times the
-// stencil's magnitude counts as zero there, so that rounding noise does not
-// pick the branch.  sgn(0) = 0; at d1 = d2 = 0, (dh/dd1, dh/dd2) = (1, 0).
-struct MwbD {
-  double dc, du1, du2;
-};
-__device__ inline MwbD mwb_grad(double aC, double K, double c, double u1, double u2, double eps) {
-  double d1 = c - u1, d2 = u1 - u2;
-  const double thr = eps * (fabs(c) + fabs(u1) + fabs(u2));
-  if (fabs(d1) <= thr) d1 = 0.0;
-  if (fabs(d2) <= thr) d2 = 0.0;
-  const double a1 = fabs(d1), a2 = fabs(d2), D = a1 + a2;
-  double h1 = 1.0, h2 = 0.0;
-  if (D != 0.0) {
-    const double s1 = d1 > 0.0 ? 1.0 : (d1 < 0.0 ? -1.0 : 0.0);
-    const double s2 = d2 > 0.0 ? 1.0 : (d2 < 0.0 ? -1.0 : 0.0);
-    const double iD = 1.0 / D, iD2 = iD * iD;
-    h1 = a1 * iD + (d1 - d2) * s1 * a2 * iD2;
-    h2 = -a1 * iD - (d1 - d2) * a1 * s2 * iD2;
-  }
-  MwbD r;
-  r.dc = aC + K * h1;
-  r.du1 = -aC - K * h1 + K * h2;
-  r.du2 = -K * h2;
-  return r;
-}
-
-// Tie threshold per storage precision: a few hundred ulps of the stored values
-// (rounding differences of f^eq scale with sum |f| / rho, up to about 16 here).
-template <class R> struct TieEps;
-template <> struct TieEps<double> { static constexpr double value = 1e-13; };
-template <> struct TieEps<float> { static constexpr double value = 1e-5; };
-
-template <class R>
-__device__ inline double fetch_f(const R* __restrict__ f, const R* __restrict__ ghost, int q, int i,
-                                 int j, int nr, int nth, size_t plane) {
-  if (i < 0) return (double)ghost[ghost_index(0, -1 - i, q, j, nth)];
-  if (i >= nr) return (double)ghost[ghost_index(1, i - nr, q, j, nth)];
-  return (double)f[q * plane + (size_t)i * nth + j];
-}
-
-template <int Q, class Fn>
-__device__ inline void static_for_q(Fn&& fn) {
-  if constexpr (Q < NQ) {
-    fn(std::integral_constant<int, Q>{});
-    static_for_q<Q + 1>(fn);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Ghost adjoint: cotangents of the ghost distributions from the MWB terms of
@@ -233,7 +120,9 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
   const size_t plane = (size_t)nr * nth;
   const size_t c0 = (size_t)i * nth + j;
   const double e = T.e;
-  constexpr double TE = TieEps<R>::value;
+  // MWB derivatives in the state's precision
+  using A = R;
+  const A TEa = (A)TieEps<R>::value;
   // moment cotangent of this node from the relaxation's f^eq
   double gM[4];
   {
@@ -289,18 +178,20 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
       const double r3 = fetch_f(f, ghost, q, i + 1, j, nr, nth, plane);
       const double r4 = fetch_f(f, ghost, q, i + 2, j, nr, nth, plane);
       // m as centre
-      acc -= lq * mwb_grad(aC, K, r2, back ? r1 : r3, back ? r0 : r4, TE).dc;
+      acc -= lq * (double)mwb_grad_t<A>((A)aC, (A)K, (A)r2, (A)(back ? r1 : r3), (A)(back ? r0 : r4), TEa).dc;
       // m as first upwind neighbour of n1 = i + 1 (backward) or i - 1 (forward)
       const int n1 = back ? i + 1 : i - 1;
       if (n1 >= 0 && n1 < nr) {
-        const MwbD g = back ? mwb_grad(aC, K, r3, r2, r1, TE) : mwb_grad(aC, K, r1, r2, r3, TE);
-        acc -= (double)lam[q * plane + (size_t)n1 * nth + j] * g.du1;
+        const MwbDT<A> g = back ? mwb_grad_t<A>((A)aC, (A)K, (A)r3, (A)r2, (A)r1, TEa)
+                                : mwb_grad_t<A>((A)aC, (A)K, (A)r1, (A)r2, (A)r3, TEa);
+        acc -= (double)lam[q * plane + (size_t)n1 * nth + j] * (double)g.du1;
       }
       // m as second upwind neighbour of n2 = i + 2 (backward) or i - 2 (forward)
       const int n2 = back ? i + 2 : i - 2;
       if (n2 >= 0 && n2 < nr) {
-        const MwbD g = back ? mwb_grad(aC, K, r4, r3, r2, TE) : mwb_grad(aC, K, r0, r1, r2, TE);
-        acc -= (double)lam[q * plane + (size_t)n2 * nth + j] * g.du2;
+        const MwbDT<A> g = back ? mwb_grad_t<A>((A)aC, (A)K, (A)r4, (A)r3, (A)r2, TEa)
+                                : mwb_grad_t<A>((A)aC, (A)K, (A)r0, (A)r1, (A)r2, TEa);
+        acc -= (double)lam[q * plane + (size_t)n2 * nth + j] * (double)g.du2;
       }
     }
     // azimuthal gather: output n = j + s - 2 with its own upwind side
@@ -313,29 +204,30 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
       vt = -vx * sn[0] + vy * cs[0];
       if (vt < 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[0]] * mwb_grad(aC, K, t0, t1, t2, TE).du2;
+        acc -= (double)lp[jj[0]] * (double)mwb_grad_t<A>((A)aC, (A)K, (A)t0, (A)t1, (A)t2, TEa).du2;
       }
       // s = 1: n = j - 1, forward (m = u1)
       vt = -vx * sn[1] + vy * cs[1];
       if (vt < 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[1]] * mwb_grad(aC, K, t1, t2, t3, TE).du1;
+        acc -= (double)lp[jj[1]] * (double)mwb_grad_t<A>((A)aC, (A)K, (A)t1, (A)t2, (A)t3, TEa).du1;
       }
       // s = 2: n = m (m is the centre)
       vt = -vx * sn[2] + vy * cs[2];
       aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-      acc -= lq * (vt >= 0.0 ? mwb_grad(aC, K, t2, t1, t0, TE) : mwb_grad(aC, K, t2, t3, t4, TE)).dc;
+      acc -= lq * (double)(vt >= 0.0 ? mwb_grad_t<A>((A)aC, (A)K, (A)t2, (A)t1, (A)t0, TEa)
+                                      : mwb_grad_t<A>((A)aC, (A)K, (A)t2, (A)t3, (A)t4, TEa)).dc;
       // s = 3: n = j + 1, backward (m = u1)
       vt = -vx * sn[3] + vy * cs[3];
       if (vt >= 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[3]] * mwb_grad(aC, K, t3, t2, t1, TE).du1;
+        acc -= (double)lp[jj[3]] * (double)mwb_grad_t<A>((A)aC, (A)K, (A)t3, (A)t2, (A)t1, TEa).du1;
       }
       // s = 4: n = j + 2, backward (m = u2)
       vt = -vx * sn[4] + vy * cs[4];
       if (vt >= 0.0) {
         aC = fabs(vt * sth_row); K = aC * (1.0 - aC);
-        acc -= (double)lp[jj[4]] * mwb_grad(aC, K, t4, t3, t2, TE).du2;
+        acc -= (double)lp[jj[4]] * (double)mwb_grad_t<A>((A)aC, (A)K, (A)t4, (A)t3, (A)t2, TEa).du2;
       }
     }
     out[q * plane + c0] = (R)acc;
@@ -375,7 +267,7 @@ __global__ void __launch_bounds__(128) adjoint_init_kernel(Tables T, const R* __
 
 template <class R>
 hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const void* lam,
-                          void* lam_out, void* ghost, void* /*unused*/, double* gm, hipStream_t s) {
+                          void* lam_out, void* ghost, double* gm, hipStream_t s) {
   hipError_t e = launch_ghost<R>(T, bc, f, ghost, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ghost_adjoint_kernel<R>, dim3((T.nth + 127) / 128, 2), dim3(128), 0, s, T, bc,
@@ -397,9 +289,9 @@ hipError_t launch_adjoint_init(const Tables& T, const void* lam, const double* r
 }
 
 template hipError_t launch_adjoint<float>(const Tables&, const BCdev&, const void*, const void*, void*,
-                                          void*, void*, double*, hipStream_t);
+                                          void*, double*, hipStream_t);
 template hipError_t launch_adjoint<double>(const Tables&, const BCdev&, const void*, const void*, void*,
-                                           void*, void*, double*, hipStream_t);
+                                           void*, double*, hipStream_t);
 template hipError_t launch_adjoint_init<float>(const Tables&, const void*, const double*, const double*,
                                                const double*, const double*, double*, double*, double*,
                                                double*, hipStream_t);

@@ -23,22 +23,13 @@
 
 #include "common.h"
 #include "launch.h"
+#include "strip_common.h"
 
 namespace pclb {
 
 namespace {
 
-constexpr int WAVE = 64;
-constexpr int HALO = 2;
-constexpr int OUT_COLS = WAVE - 2 * HALO;     // 60 output columns per strip
-// word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format)
-constexpr int BUF_DWORD3 = 0x00020000;
-constexpr int NXCD = 8;   // accelerator dies; workgroups are dealt to them round-robin
-// Byte offset beyond the buffers' range: a raw buffer access at this offset
-// is discarded by the hardware range check (a load returns 0).  Used for the
-// halo lanes' stores and the look-ahead loads past a chunk's last row, so that
-// neither needs a branch.
-constexpr uint32_t OOB = 0x80000000u;
+using namespace strip;
 
 // The state is addressed through buffer resources, one per speed k, whose
 // base is plane 8(k-1): velocity (k, d) is plane 1 + d of resource k-1 and
@@ -54,18 +45,6 @@ struct StripCtx {
   bool store;               // this lane writes an output (not a halo column)
   double e, ome;            // exp(-dt/tau) and 1 - exp(-dt/tau)
 };
-
-template <int V, int N, class Fn>
-__device__ inline void for_v(Fn&& fn) {
-  if constexpr (V < N) {
-    fn(std::integral_constant<int, V>{});
-    for_v<V + 1, N>(fn);
-  }
-}
-
-__device__ inline float lane_from(float v, int byte_addr) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
-}
 
 // Work split: a strip is processed by NSPLIT wavefronts of one workgroup.
 // Wave W owns the direction pairs d4 = D40 .. D40 + D4N - 1 and, for each,
@@ -311,17 +290,7 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   __shared__ double lds[NSPLIT > 1 ? 2 * 16 * 64 : 1];
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x >> 6;                     // wave within the group
-  // Work item w runs over strips first, then chunks.  With xcd_order the
-  // workgroups dealt to one XCD take a contiguous range of work items, so
-  // that strips next to each other in theta (which read the same cache lines
-  // at their common edge) and the chunks above and below them share that
-  // XCD's L2.
-  int w_item = blockIdx.x;
-  if (xcd_order) {
-    const int nb = gridDim.x, per = nb / NXCD, extra = nb % NXCD;
-    const int x = blockIdx.x % NXCD, local = blockIdx.x / NXCD;
-    w_item = x * per + min(x, extra) + local;
-  }
+  const int w_item = work_item(xcd_order);
   const int strip = w_item % n_strips;
   const int chunk = w_item / n_strips;
   const int nr = T.nr, nth = T.nth;
@@ -333,12 +302,10 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   X.plane_bytes = (uint32_t)(plane * 4);
 #pragma unroll
   for (int k = 1; k <= NK; ++k) {
-    X.fin[k - 1] = __builtin_amdgcn_make_buffer_rsrc((void*)(f + ND * (k - 1) * plane), 0,
-                                                     0x7fffffff, BUF_DWORD3);
-    X.fout[k - 1] = __builtin_amdgcn_make_buffer_rsrc((void*)(out + ND * (k - 1) * plane), 0,
-                                                      0x7fffffff, BUF_DWORD3);
+    X.fin[k - 1] = make_rsrc(f + ND * (k - 1) * plane);
+    X.fout[k - 1] = make_rsrc(out + ND * (k - 1) * plane);
   }
-  X.gh = __builtin_amdgcn_make_buffer_rsrc((void*)ghost, 0, 0x7fffffff, BUF_DWORD3);
+  X.gh = make_rsrc(ghost);
   X.nr = nr;
   X.nth = nth;
   // column of this lane (periodic) and whether it stores an output
@@ -375,7 +342,7 @@ bool strip_supported(const Tables& T) {
 
 int strip_default_chunk(const Tables& T) {
   // enough (strip, chunk) workgroups to fill 256 CUs several times over
-  const int strips = (T.nth + OUT_COLS - 1) / OUT_COLS;
+  const int strips = n_strips(T.nth);
   int chunk = 32;
   while (chunk > 8 && (long)strips * ((T.nr + chunk - 1) / chunk) < 4096) chunk /= 2;
   return chunk;
@@ -388,7 +355,7 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
   const int chunk_rows = tune.chunk > 0 ? tune.chunk : strip_default_chunk(T);
   const int split = tune.split > 0 ? tune.split : 2;
   const int order = tune.order >= 0 ? (tune.order ? 1 : 0) : 1;
-  const int strips = (T.nth + OUT_COLS - 1) / OUT_COLS;
+  const int strips = n_strips(T.nth);
   const int chunks = (T.nr + chunk_rows - 1) / chunk_rows;
   const int blocks = strips * chunks;
   const float* fi = (const float*)f;

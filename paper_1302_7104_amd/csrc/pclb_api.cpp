@@ -315,8 +315,8 @@ int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* 
   if (!f_t || !lam_next || !lam_out || lam_out == lam_next || lam_out == f_t)
     return fail(c, PCLB_EINVAL, "three non-null buffers, lam_out distinct from the inputs");
   hipError_t e = c->cfg.precision == 32
-                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, nullptr, c->d_gm, c->stream)
-                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, nullptr, c->d_gm, c->stream);
+                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->stream)
+                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
   return PCLB_OK;
 }
