@@ -80,23 +80,23 @@ def run_forward(W, Sim, torch, precision, steps, warmup, nr=4096, nth=8192):
     return P, ms, d
 
 
-def run_adjoint(W, torch, steps=200, ckpt=20, precision=32):
-    from paper_1302_7104_amd.sim import Evolve, InitState, Sim
-    P, F = W.richtmyer_meshkov(1024, 2048, steps)
+def adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, precision):
+    """J = sum over 1.1 < r < 1.5 of rho^2 r dr dtheta after `steps` steps of
+    the Richtmyer-Meshkov recipe, and dJ/da_k through the hand-written
+    adjoint with checkpoint-recompute.  Returns (J, grad, forward ms/step,
+    backward ms/step)."""
     sim = Sim(P, precision=precision)
     dev = sim.device
     amps = torch.as_tensor(W.rm_amplitudes(1), device=dev).requires_grad_(True)
-    _, Ft = W.richtmyer_meshkov(1024, 2048, steps, amps=amps, xp=torch)
+    _, Ft = W.richtmyer_meshkov(P.nr, P.nth, steps, amps=amps, xp=torch)
     f0 = InitState.apply(sim, Ft["rho"], Ft["ur"], Ft["ut"], Ft["T"])
     torch.cuda.synchronize()
-    # forward alone (no checkpoints): the reference cost
     sim.load_state(f0.detach())
     ms_fwd = time_steps(sim, torch, steps)
     R, _ = W.node_coords(P.nr, P.nth, P.r1, P.r2)
     band = torch.as_tensor(((R > 1.1) & (R < 1.5)) * R * P.dr * P.dth, device=dev,
-                           dtype=torch.float32 if precision == 32 else torch.float64)
+                           dtype=sim.dtype)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     fn = Evolve.apply(sim, f0, steps, ckpt)
     J = ((fn.sum(0) ** 2) * band).sum()
     torch.cuda.synchronize()
@@ -104,17 +104,64 @@ def run_adjoint(W, torch, steps=200, ckpt=20, precision=32):
     J.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    grad = amps.grad.detach().cpu().numpy().tolist()
+    grad = amps.grad.detach().cpu().numpy()
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    ms_bwd_per_step = (t2 - t1) * 1e3 / steps
-    return dict(ms_forward_step=ms_fwd, ms_forward_with_checkpoints=(t1 - t0) * 1e3 / steps,
-                ms_backward_per_step=ms_bwd_per_step,
-                adjoint_over_forward=ms_bwd_per_step / ms_fwd, dJ_da=grad, J=float(J.item()))
+    return float(J.item()), grad, ms_fwd, (t2 - t1) * 1e3 / steps
 
 
-def cpu_baseline(W, target_s=12.0):
+def fd_gradient(W, torch, Sim, P, steps, h):
+    """Central differences of J in a_k with the FP64 forward."""
+    import numpy as np
+    sim = Sim(P, precision=64)
+    R, _ = W.node_coords(P.nr, P.nth, P.r1, P.r2)
+    band = torch.as_tensor(((R > 1.1) & (R < 1.5)) * R * P.dr * P.dth, device=sim.device)
+    a0 = W.rm_amplitudes(1)
+
+    def J_of(a):
+        _, F = W.richtmyer_meshkov(P.nr, P.nth, steps, amps=a)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        sim.step(steps)
+        return float(((sim.state.sum(0) ** 2) * band).sum().item())
+
+    fd = np.array([(J_of(a0 + h * np.eye(13)[k]) - J_of(a0 - h * np.eye(13)[k])) / (2 * h)
+                   for k in range(13)])
+    sim.close()
+    return fd
+
+
+def run_adjoint(W, torch, steps=200, ckpt=20):
+    """The 1024 x 2048 Richtmyer-Meshkov adjoint configuration: cost of the
+    FP32 backward pass relative to the FP32 forward step, the FP32 and FP64
+    gradients, and their agreement with FP64 central differences."""
+    import numpy as np
+    from paper_1302_7104_amd.sim import Evolve, InitState, Sim
+    P, _ = W.richtmyer_meshkov(1024, 2048, steps)
+    J32, g32, fwd32, bwd32 = adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, 32)
+    J64, g64, fwd64, bwd64 = adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, 64)
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    fd = {}
+    for n, h in ((steps, 1e-4), (steps, 1e-6), (20, 1e-6)):
+        P_n, _ = W.richtmyer_meshkov(1024, 2048, n)
+        f = fd_gradient(W, torch, Sim, P_n, n, h)
+        g_n = g64 if n == steps else adjoint_gradient(W, torch, Sim, Evolve, InitState, P_n, n,
+                                                      ckpt, 64)[1]
+        fd[f"{n}_steps_h{h:g}"] = {"fp64_adjoint_vs_fd": rel(g_n, f)}
+        if n == steps:
+            fd[f"{n}_steps_h{h:g}"]["fp32_adjoint_vs_fd"] = rel(g32, f)
+    return dict(ms_forward_step=fwd32, ms_backward_per_step=bwd32,
+                adjoint_over_forward=bwd32 / fwd32,
+                fp64_ms_forward_step=fwd64, fp64_ms_backward_per_step=bwd64,
+                fp64_adjoint_over_forward=bwd64 / fwd64,
+                J_fp32=J32, J_fp64=J64, dJ_da_fp32=g32.tolist(), dJ_da_fp64=g64.tolist(),
+                fp32_vs_fp64_gradient=rel(g32, g64), finite_differences=fd)
+
+
+def cpu_baseline(W, target_s=15.0):
     """The FP64 CPU oracle, as it stands, on the same recipe at 512 x 1024
     (cost per cell-velocity update does not depend on the grid size)."""
     from oracle import oracle as O
@@ -122,9 +169,10 @@ def cpu_baseline(W, target_s=12.0):
     P, F = W.kelvin_helmholtz(512, 1024, 1)
     g = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par)
     f = O.init_feq(g, **F)
+    f, _ = O.step(g, f, 1)                       # thread pool start-up
     t0 = time.perf_counter()
-    f, _ = O.step(g, f, 1)
-    one = time.perf_counter() - t0
+    f, _ = O.step(g, f, 2)
+    one = (time.perf_counter() - t0) / 2
     n = max(1, int(target_s / max(one, 1e-3)))
     t0 = time.perf_counter()
     f, _ = O.step(g, f, n)

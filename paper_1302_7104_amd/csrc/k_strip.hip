@@ -1,11 +1,12 @@
 // Strip kernel of the combined-scheme step (Eq. combined_scheme) for FP32
 // storage.  A workgroup owns a strip of 64 consecutive theta columns (one per
-// lane) and marches in r over a chunk of rows.  For each velocity a wavefront
-// keeps the three rows its radial MWB stencil needs (centre and the two
-// upwind neighbours) in registers, so every f value of the chunk is read from
-// HBM once.  The azimuthal neighbours come from the adjacent lanes
-// (ds_bpermute); the two lanes at each end of the strip are halo columns that
-// produce no output, so consecutive strips start 60 columns apart.
+// lane, the strip aligned to 64 columns so that every load and store covers
+// whole cache lines) and marches in r over a chunk of rows.  For each velocity
+// a wavefront keeps the three rows its radial MWB stencil needs (centre and
+// the two upwind neighbours) in registers, so every f value of the chunk is
+// read from HBM once.  The azimuthal neighbours come from the adjacent lanes
+// (ds_bpermute); the two columns beyond the strip on the upwind side are read
+// per row by the edge lane (one 8-byte load per velocity).
 //
 // Per row: moments, equilibrium and analytic relaxation in double (Eqs.
 // moment1-3, F_k, feq, operator1_new), the radial and azimuthal MWB terms in
@@ -42,8 +43,14 @@ struct StripCtx {
   int nr, nth;
   int col;                  // this lane's column
   uint32_t col4;            // its byte offset within a row
-  bool store;               // this lane writes an output (not a halo column)
+  bool store;               // this lane's column exists (the last strip may be ragged)
   double e, ome;            // exp(-dt/tau) and 1 - exp(-dt/tau)
+  // azimuthal halo: byte offsets within a row of the columns the edge lanes read
+  uint32_t hl4, hr4;        // pair (j0-2, j0-1) for lane 0, pair (j0+64, j0+65) for lane 63
+  uint32_t hu1_4, hu2_4;    // mixed strips: u1 of lanes 0 / 63, u2 of lanes 0, 1 / 62, 63
+  bool edge_l, edge_r;      // lane 0, lane 63
+  bool e2l, e2r;            // lanes 0 and 1, lanes 62 and 63
+  bool halo_pairs;          // the 8-byte halo loads apply (uniform waves)
 };
 
 // Work split: a strip is processed by NSPLIT wavefronts of one workgroup.
@@ -71,6 +78,7 @@ struct Roles {
   uint32_t soff[D4N][2];    // byte offset of member h's plane within its resource
   int qb[D4N][2];           // 1 + direction of member h (its plane within the resource)
   double sg[D4N];           // +1, or -1 when the members are swapped
+  bool tb[D4N][2];          // uniform waves: member h is azimuthally upwind-backward
 };
 
 // Load of a slot's velocity (speed K, plane qb of resource K-1) at row `row`;
@@ -100,6 +108,29 @@ __device__ inline uint32_t row_off(const StripCtx& X, int row, bool on) {
   return on ? (uint32_t)(row * X.nth) * 4u + X.col4 : OOB;
 }
 
+// Azimuthal halo of one velocity at row `row` (a real row).  Uniform waves:
+// the edge lane on the upwind side reads the two columns beyond the strip in
+// one 8-byte load, (lo, hi) = (j0-2, j0-1) on the left, (j0+64, j0+65) on the
+// right.  Mixed waves: lanes 0 / 63 read their u1 into `lo`, lanes 0, 1 /
+// 62, 63 their u2 into `hi`.  Every other lane reads nothing (value 0).
+template <int K, bool UNI>
+__device__ inline void load_halo(const StripCtx& X, uint32_t soff, int row, bool tb, bool on,
+                                 float& lo, float& hi) {
+  const uint32_t rb = (uint32_t)(row * X.nth) * 4u;
+  if constexpr (UNI) {
+    const bool act = on && (tb ? X.edge_l : X.edge_r);
+    const uint32_t voff = act ? rb + (tb ? X.hl4 : X.hr4) : OOB;
+    const auto r = __builtin_amdgcn_raw_buffer_load_b64(X.fin[K - 1], voff, soff, 0);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
+  } else {
+    const uint32_t v1 = on && (X.edge_l || X.edge_r) ? rb + X.hu1_4 : OOB;
+    const uint32_t v2 = on && (X.e2l || X.e2r) ? rb + X.hu2_4 : OOB;
+    lo = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(X.fin[K - 1], v1, soff, 0));
+    hi = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(X.fin[K - 1], v2, soff, 0));
+  }
+}
+
 // One output row i.  For every owned velocity the slots A, B, C hold three
 // consecutive rows in increasing order: (i-2, i-1, i) when the upwind side is
 // i-1 ("backward"), (i, i+1, i+2) otherwise.  After the velocity's terms are
@@ -108,7 +139,8 @@ __device__ inline uint32_t row_off(const StripCtx& X, int row, bool on) {
 template <int NSPLIT, int W, bool EDGE, bool UNI>
 __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                  const Roles<4 / NSPLIT>& RL, int i, bool more, const int* ta,
-                                 float& r0, float* A, float* B, float* C, double* lds) {
+                                 float& r0, float* A, float* B, float* C, float* HA, float* HB,
+                                 double* lds) {
   using O = Own<NSPLIT, W>;
   const int lane = threadIdx.x & 63;
   // backward role of slot v: fixed in a uniform wave, per lane otherwise
@@ -178,20 +210,37 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
     auto one = [&](auto vv, bool bk, float c, float rl) {
       constexpr int v = decltype(vv)::value;
       constexpr int h = O::h_of(v);
-      // azimuthal differences: d1 from the upwind lane; d2 is that lane's d1
-      // where every lane has the same upwind side (uniform waves), else it is
-      // formed from the value two lanes upwind
-      const float u1t = lane_from(c, ta[v]);
-      const float d1t = c - u1t;
-      float d2t;
-      if constexpr (UNI) d2t = lane_from(d1t, ta[v]);
-      else d2t = u1t - lane_from(c, (ta[v] << 1) - (lane << 2));
+      // azimuthal differences.  Uniform waves: d1 from the upwind lane (the
+      // edge lane from the halo), d2 is the upwind lane's d1 (the edge lane's
+      // from the halo pair).  Mixed waves: both neighbours from the lanes one
+      // and two upwind, the edge lanes from their halo values.
+      float d1t, d2t;
+      if constexpr (UNI) {
+        const bool tb = RL.tb[pl][h];
+        const bool edge = tb ? X.edge_l : X.edge_r;
+        const float fix1 = tb ? HB[v] : HA[v], fix2 = tb ? HA[v] : HB[v];
+        const float z = lane_from(c, ta[v]);
+        const float u1t = edge ? fix1 : z;
+        d1t = c - u1t;
+        const float dz = lane_from(d1t, ta[v]);
+        d2t = edge ? fix1 - fix2 : dz;
+      } else {
+        const bool tb = (G.tback >> (O::D40 + O::pl_of(v) + 4 * O::h_of(v))) & 1u;
+        const bool e1 = tb ? X.edge_l : X.edge_r, e2 = tb ? X.e2l : X.e2r;
+        const float z1 = lane_from(c, ta[v]);
+        const float z2 = lane_from(c, (ta[v] << 1) - (lane << 2));
+        const float u1t = e1 ? HA[v] : z1;
+        const float u2t = e2 ? HB[v] : z2;
+        d1t = c - u1t;
+        d2t = u1t - u2t;
+      }
       const float u1r = B[v];
       const float d1r = c - u1r, d2r = u1r - (bk ? A[v] : C[v]);
       const float res = mwb_update_d<float>(rl, aCr, Kr, d1r, d2r, aCt, Kt, d1t, d2t);
       store_slot<k>(X, RL.soff[pl][h], ovoff, res);
       A[v] = load_slot<EDGE, k>(X, RL.soff[pl][h], RL.qb[pl][h], bk ? i + 1 : i + 3, bk ? vb : vf,
                                 more);
+      load_halo<k, UNI>(X, RL.soff[pl][h], i + 1, UNI ? RL.tb[pl][h] : false, more, HA[v], HB[v]);
     };
     one(std::integral_constant<int, v0>{}, b0, c0, rel[0]);
     one(std::integral_constant<int, v1>{}, b1, c1, rel[1]);
@@ -204,6 +253,7 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
                                    double* lds) {
   using O = Own<NSPLIT, W>;
   float S0[O::NV], S1[O::NV], S2[O::NV];
+  float HA[O::NV], HB[O::NV];     // azimuthal halo of the current row, per slot
   // ds_bpermute byte address of the azimuthally upwind lane, per slot
   int ta[O::NV];
   const int lane = threadIdx.x & (WAVE - 1);
@@ -221,25 +271,29 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
     S0[v] = load_slot<EDGE, k>(X, so, qb, base, row_off(X, base, true), true);
     S1[v] = load_slot<EDGE, k>(X, so, qb, base + 1, row_off(X, base + 1, true), true);
     S2[v] = load_slot<EDGE, k>(X, so, qb, base + 2, row_off(X, base + 2, true), true);
+    load_halo<k, UNI>(X, so, i_begin, UNI ? RL.tb[pl][h] : false, true, HA[v], HB[v]);
   });
   for (int i = i_begin; i < i_end; i += 3) {
-    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i, i + 1 < i_end, ta, r0, S0, S1, S2, lds);
+    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i, i + 1 < i_end, ta, r0, S0, S1, S2, HA, HB, lds);
     if (i + 1 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 1, i + 2 < i_end, ta, r0, S1, S2, S0, lds);
+    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 1, i + 2 < i_end, ta, r0, S1, S2, S0, HA, HB,
+                                    lds);
     if (i + 2 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 2, i + 3 < i_end, ta, r0, S2, S0, S1, lds);
+    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 2, i + 3 < i_end, ta, r0, S2, S0, S1, HA, HB,
+                                    lds);
   }
 }
 
-template <int NSPLIT, int W>
+template <int NSPLIT, int W, bool MIXED>
 __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                   int i_begin, int i_end, double* lds) {
   using O = Own<NSPLIT, W>;
   // Roles of the owned pairs: uniform when, on every lane of the wave, exactly
   // one member of each pair is radially backward, the same member on all
-  // lanes, and each member has the same azimuthal upwind side on all lanes.
+  // lanes, and each member has the same azimuthal upwind side on all lanes
+  // (and the two halo columns on each side are adjacent in memory).
   Roles<O::D4N> RL;
-  bool uni = true;
+  bool uni = X.halo_pairs;
 #pragma unroll
   for (int pl = 0; pl < O::D4N; ++pl) {
     const int d4 = O::D40 + pl;
@@ -257,11 +311,21 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
       const int qb = 1 + d4 + 4 * (h ^ (swap ? 1 : 0));
       RL.qb[pl][h] = qb;
       RL.soff[pl][h] = (uint32_t)qb * X.plane_bytes;
+      RL.tb[pl][h] = (h ^ (swap ? 1 : 0)) ? t1 == all : t0 == all;
     }
   }
   // the chunk reads rows i_begin-2 .. i_end+1; only chunks next to a wall
   // touch the ghost layers
   const bool edge = i_begin < 2 || i_end + 1 >= X.nr;
+  // Strips where every wave is uniform run in the launch without the mixed
+  // code (which needs more registers); the others in the mixed launch.
+  const bool all_uni = __syncthreads_and(uni ? 1 : 0) != 0;
+  if (all_uni == MIXED) return;
+  if constexpr (!MIXED) {
+    if (edge) strip_march<NSPLIT, W, true, true>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, true>(T, X, G, RL, i_begin, i_end, lds);
+    return;
+  }
   if (uni) {
     if (edge) strip_march<NSPLIT, W, true, true>(T, X, G, RL, i_begin, i_end, lds);
     else strip_march<NSPLIT, W, false, true>(T, X, G, RL, i_begin, i_end, lds);
@@ -274,6 +338,7 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
         const int qb = 1 + O::D40 + pl + 4 * h;
         RL.qb[pl][h] = qb;
         RL.soff[pl][h] = (uint32_t)qb * X.plane_bytes;
+        RL.tb[pl][h] = false;
       }
     }
     if (edge) strip_march<NSPLIT, W, true, false>(T, X, G, RL, i_begin, i_end, lds);
@@ -283,7 +348,7 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
 
 }  // namespace
 
-template <int NSPLIT>
+template <int NSPLIT, bool MIXED>
 __global__ void __launch_bounds__(WAVE * NSPLIT)
 step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out,
                   const float* __restrict__ ghost, int chunk_rows, int n_strips, int xcd_order) {
@@ -309,25 +374,41 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   X.nr = nr;
   X.nth = nth;
   // column of this lane (periodic) and whether it stores an output
-  const int jout = strip * OUT_COLS + lane - HALO;     // may be -2 .. nth+1
-  int col = jout % nth;
-  X.col = col < 0 ? col + nth : col;
+  const int j0 = strip * WAVE;
+  const int jout = j0 + lane;                          // past nth only in a ragged last strip
+  X.col = jout % nth;
   X.col4 = (uint32_t)X.col * 4u;
-  X.store = lane >= HALO && lane < WAVE - HALO && jout < nth;
+  X.store = jout < nth;
+  // azimuthal halo columns (periodic)
+  auto wrap = [&](int c) { return ((c % nth) + nth) % nth; };
+  X.edge_l = lane == 0;
+  X.edge_r = lane == WAVE - 1;
+  X.e2l = lane <= 1;
+  X.e2r = lane >= WAVE - 2;
+  X.hl4 = (uint32_t)wrap(j0 - 2) * 4u;
+  X.hr4 = (uint32_t)wrap(j0 + WAVE) * 4u;
+  X.hu1_4 = (uint32_t)(lane == 0 ? wrap(j0 - 1) : wrap(j0 + WAVE)) * 4u;
+  X.hu2_4 = (uint32_t)(lane == 0 ? wrap(j0 - 2)
+                                 : lane == 1 ? wrap(j0 - 1)
+                                             : lane == WAVE - 2 ? wrap(j0 + WAVE) : wrap(j0 + WAVE + 1)) *
+            4u;
+  // the 8-byte halo loads need both pairs adjacent and 8-byte aligned
+  X.halo_pairs = (nth % 2 == 0) && wrap(j0 - 2) + 1 == wrap(j0 - 1) &&
+                 wrap(j0 + WAVE) + 1 == wrap(j0 + WAVE + 1);
   X.e = T.e;
   X.ome = 1.0 - T.e;
   DirGeom<float> G;
   dir_geometry(T.cth[X.col], T.sth[X.col], T.dt_dr, T.dt_dth, G);
   if constexpr (NSPLIT == 1) {
-    strip_wave<1, 0>(T, X, G, i_begin, i_end, lds);
+    strip_wave<1, 0, MIXED>(T, X, G, i_begin, i_end, lds);
   } else if constexpr (NSPLIT == 2) {
-    if (w == 0) strip_wave<2, 0>(T, X, G, i_begin, i_end, lds);
-    else strip_wave<2, 1>(T, X, G, i_begin, i_end, lds);
+    if (w == 0) strip_wave<2, 0, MIXED>(T, X, G, i_begin, i_end, lds);
+    else strip_wave<2, 1, MIXED>(T, X, G, i_begin, i_end, lds);
   } else {
-    if (w == 0) strip_wave<4, 0>(T, X, G, i_begin, i_end, lds);
-    else if (w == 1) strip_wave<4, 1>(T, X, G, i_begin, i_end, lds);
-    else if (w == 2) strip_wave<4, 2>(T, X, G, i_begin, i_end, lds);
-    else strip_wave<4, 3>(T, X, G, i_begin, i_end, lds);
+    if (w == 0) strip_wave<4, 0, MIXED>(T, X, G, i_begin, i_end, lds);
+    else if (w == 1) strip_wave<4, 1, MIXED>(T, X, G, i_begin, i_end, lds);
+    else if (w == 2) strip_wave<4, 2, MIXED>(T, X, G, i_begin, i_end, lds);
+    else strip_wave<4, 3, MIXED>(T, X, G, i_begin, i_end, lds);
   }
 }
 
@@ -361,18 +442,38 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
   const float* fi = (const float*)f;
   float* fo = (float*)out;
   const float* gh = (const float*)ghost;
-  if (split == 1)
-    hipLaunchKernelGGL(step_strip_kernel<1>, dim3(blocks), dim3(WAVE), 0, s, T, fi, fo, gh,
-                       chunk_rows, strips, order);
-  else if (split == 2)
-    hipLaunchKernelGGL(step_strip_kernel<2>, dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo, gh,
-                       chunk_rows, strips, order);
-  else if (split == 4)
-    hipLaunchKernelGGL(step_strip_kernel<4>, dim3(blocks), dim3(4 * WAVE), 0, s, T, fi, fo, gh,
-                       chunk_rows, strips, order);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  // two launches over the same grid: strips whose waves are all uniform,
+  // then the others (each block of one launch returns at once in the other)
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    if (split == 1) {
+      if (m == 0)
+        hipLaunchKernelGGL((step_strip_kernel<1, false>), dim3(blocks), dim3(WAVE), 0, s, T, fi, fo,
+                           gh, chunk_rows, strips, order);
+      else
+        hipLaunchKernelGGL((step_strip_kernel<1, true>), dim3(blocks), dim3(WAVE), 0, s, T, fi, fo,
+                           gh, chunk_rows, strips, order);
+    } else if (split == 2) {
+      if (m == 0)
+        hipLaunchKernelGGL((step_strip_kernel<2, false>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi,
+                           fo, gh, chunk_rows, strips, order);
+      else
+        hipLaunchKernelGGL((step_strip_kernel<2, true>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi,
+                           fo, gh, chunk_rows, strips, order);
+    } else if (split == 4) {
+      if (m == 0)
+        hipLaunchKernelGGL((step_strip_kernel<4, false>), dim3(blocks), dim3(4 * WAVE), 0, s, T, fi,
+                           fo, gh, chunk_rows, strips, order);
+      else
+        hipLaunchKernelGGL((step_strip_kernel<4, true>), dim3(blocks), dim3(4 * WAVE), 0, s, T, fi,
+                           fo, gh, chunk_rows, strips, order);
+    } else {
+      return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template bool strip_supported<float>(const Tables&);

@@ -11,16 +11,15 @@
 namespace pclb {
 namespace strip {
 
-constexpr int WAVE = 64;
-constexpr int HALO = 2;
-constexpr int OUT_COLS = WAVE - 2 * HALO;     // 60 output columns per strip
+constexpr int WAVE = 64;                       // one strip = 64 theta columns, one per lane
 // word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format)
 constexpr int BUF_DWORD3 = 0x00020000;
 constexpr int NXCD = 8;   // accelerator dies; workgroups are dealt to them round-robin
 // Byte offset beyond the buffers' range: a raw buffer access at this offset
 // is discarded by the hardware range check (a load returns 0).  Used for the
-// halo lanes' stores and the look-ahead loads past a chunk's last row, so that
-// neither needs a branch.
+// stores of lanes past the last column, the look-ahead loads past a chunk's
+// last row and the halo loads of lanes that read no halo, so that none of them
+// needs a branch.
 constexpr uint32_t OOB = 0x80000000u;
 
 template <int V, int N, class Fn>
@@ -54,7 +53,7 @@ __device__ inline int work_item(int xcd_order) {
   return w;
 }
 
-inline int n_strips(int nth) { return (nth + OUT_COLS - 1) / OUT_COLS; }
+inline int n_strips(int nth) { return (nth + WAVE - 1) / WAVE; }
 
 }  // namespace strip
 }  // namespace pclb
