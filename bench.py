@@ -31,7 +31,7 @@ NQ = 33
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("common.h", "k_strip.hip", "k_forward.hip"):
+    for name in ("common.h", "strip_common.h", "k_strip.hip", "k_forward.hip"):
         with open(os.path.join(ROOT, "paper_1302_7104_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -247,6 +247,32 @@ def test_node_and_strip_kernels_bitwise_equal():
         assert np.array_equal(res[0], res[1]), prec
 
 
+@pytest.mark.parametrize("shape", [(33, 66), (12, 64), (9, 129), (20, 4000), (40, 250)])
+def test_strip_launch_shapes_bitwise_equal_node_kernel(shape, monkeypatch):
+    """The FP32 strip kernel in every launch shape (wavefronts per strip,
+    rows per chunk, workgroup order) equals the node kernel bit for bit:
+    ragged last strips, odd N_theta (halo pairs not adjacent), a single strip,
+    strips with and without sign changes inside, chunks of 1 to 7 rows."""
+    from paper_1302_7104_amd import _native as N
+    nr, nth = shape
+    P, F = W.kelvin_helmholtz(nr, nth, 6)
+    s = sim_of(P, 32, N.KERNEL_NODE)
+    s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    s.step(6)
+    want = s.state.cpu().numpy()
+    s.close()
+    for split, chunk, order in [(1, 0, 1), (2, 0, 1), (4, 0, 1), (2, 7, 0), (2, 1, 1), (4, 3, 0)]:
+        monkeypatch.setenv("PCLB_STRIP_SPLIT", str(split))
+        monkeypatch.setenv("PCLB_STRIP_CHUNK", str(chunk))
+        monkeypatch.setenv("PCLB_STRIP_ORDER", str(order))
+        s = sim_of(P, 32, N.KERNEL_STRIP)
+        s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        s.step(6)
+        got = s.state.cpu().numpy()
+        s.close()
+        assert np.array_equal(got, want), (shape, split, chunk, order)
+
+
 def test_init_rejects_bad_fields():
     from paper_1302_7104_amd._native import PclbError
     P, F = smooth_problem(8, 16, BCS[0], 6)
