@@ -225,11 +225,14 @@ def summarize_counters(fetch_csv, write_csv, nodes, precision=32, copy_gib=1):
     def vals(d, key):
         return [v for k, vs in d.items() if key in k for v in vs]
 
-    # the copy of known size is the largest copy dispatch; the step kernel is
-    # averaged over its launches
+    # the copy of known size is the largest copy dispatch; a step launches the
+    # ghost kernel once and the strip kernel twice (uniform strips, then the
+    # others): bytes per step = all strip-kernel dispatches / ghost dispatches
     f_copy, w_copy = max(vals(fetch, "copyBuffer")), max(vals(write, "copyBuffer"))
-    fs, ws = vals(fetch, "step_strip_kernel"), vals(write, "step_strip_kernel")
-    f_step, w_step = sum(fs) / len(fs), sum(ws) / len(ws)
+    n_steps = len(vals(fetch, "ghost_kernel"))
+    assert n_steps == len(vals(write, "ghost_kernel")) and n_steps > 0
+    f_step = sum(vals(fetch, "step_strip_kernel")) / n_steps
+    w_step = sum(vals(write, "step_strip_kernel")) / n_steps
     f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
     rec = {"source_hash": kernel_source_hash(),
            f"fp{precision}": {"nodes": nodes, "fetch_bytes": f_step * f_scale,

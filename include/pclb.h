@@ -60,11 +60,18 @@ enum {
   PCLB_EXTRAPOLATE = 2   /* u_r, u_theta extrapolated linearly like rho and T */
 };
 
-/* Kernel selection for pclb_step / pclb_step_into. */
+/* Kernel selection for pclb_step / pclb_step_into.  Both kernels give the
+ * same result bit for bit.  The strip kernel runs FP32 states with
+ * n_theta >= 64 and 9 * 4 * n_r * n_theta < 2^31 bytes; elsewhere the node
+ * kernel runs whatever is asked.  Its launch shape can be overridden, for
+ * tuning only, with the environment variables PCLB_STRIP_CHUNK (rows per
+ * workgroup), PCLB_STRIP_SPLIT (1, 2 or 4 wavefronts per strip) and
+ * PCLB_STRIP_ORDER (1 XCD-contiguous workgroup order, 0 plain), read by
+ * pclb_create. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
-  PCLB_KERNEL_STRIP = 2    /* r-marching theta strips with a register ring */
+  PCLB_KERNEL_STRIP = 2    /* r-marching 64-column theta strips with a register ring */
 };
 
 typedef struct pclb_config {

@@ -134,8 +134,8 @@ __device__ inline void load_halo(const StripCtx& X, uint32_t soff, int row, bool
 // One output row i.  For every owned velocity the slots A, B, C hold three
 // consecutive rows in increasing order: (i-2, i-1, i) when the upwind side is
 // i-1 ("backward"), (i, i+1, i+2) otherwise.  After the velocity's terms are
-// computed, the lowest slot A is refilled with row (lowest + 3), so that the
-// roles rotate A <- B <- C <- A from one row to the next.
+// computed, the lowest slot A is refilled with row (lowest + 3), and the
+// caller rotates the roles A <- B <- C <- A for the next row.
 template <int NSPLIT, int W, bool EDGE, bool UNI>
 __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                  const Roles<4 / NSPLIT>& RL, int i, bool more, const int* ta,
@@ -273,14 +273,16 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
     S2[v] = load_slot<EDGE, k>(X, so, qb, base + 2, row_off(X, base + 2, true), true);
     load_halo<k, UNI>(X, so, i_begin, UNI ? RL.tb[pl][h] : false, true, HA[v], HB[v]);
   });
-  for (int i = i_begin; i < i_end; i += 3) {
+  // one row per iteration; the ring rotates by register moves
+  for (int i = i_begin; i < i_end; ++i) {
     strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i, i + 1 < i_end, ta, r0, S0, S1, S2, HA, HB, lds);
-    if (i + 1 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 1, i + 2 < i_end, ta, r0, S1, S2, S0, HA, HB,
-                                    lds);
-    if (i + 2 >= i_end) break;
-    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i + 2, i + 3 < i_end, ta, r0, S2, S0, S1, HA, HB,
-                                    lds);
+    for_v<0, O::NV>([&](auto vc) {
+      constexpr int v = decltype(vc)::value;
+      const float t = S0[v];
+      S0[v] = S1[v];
+      S1[v] = S2[v];
+      S2[v] = t;
+    });
   }
 }
 

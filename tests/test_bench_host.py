@@ -40,14 +40,23 @@ def test_counter_scaling(tmp_path):
     # WRITE units (1024 B each); a small copy and two step launches besides
     f = tmp_path / "fetch.csv"
     w = tmp_path / "write.csv"
+    # two steps: ghost kernel, uniform-strip launch, mixed-strip launch each
     _write_counters(f, "FETCH_SIZE", [(1, "__amd_rocclr_copyBuffer", 3.0),
-                                      (2, "void pclb::step_strip_kernel<2, false>", 1000.0),
-                                      (3, "void pclb::step_strip_kernel<2, false>", 3000.0),
-                                      (4, "__amd_rocclr_copyBuffer", 524288.0)])
+                                      (2, "void pclb::ghost_kernel<float>", 7.0),
+                                      (3, "void pclb::step_strip_kernel<2, false>", 1000.0),
+                                      (4, "void pclb::step_strip_kernel<2, true>", 100.0),
+                                      (5, "void pclb::ghost_kernel<float>", 7.0),
+                                      (6, "void pclb::step_strip_kernel<2, false>", 2800.0),
+                                      (7, "void pclb::step_strip_kernel<2, true>", 100.0),
+                                      (8, "__amd_rocclr_copyBuffer", 524288.0)])
     _write_counters(w, "WRITE_SIZE", [(1, "__amd_rocclr_copyBuffer", 1.0),
-                                      (2, "void pclb::step_strip_kernel<2, false>", 500.0),
-                                      (3, "void pclb::step_strip_kernel<2, false>", 1500.0),
-                                      (4, "__amd_rocclr_copyBuffer", 1048576.0)])
+                                      (2, "void pclb::ghost_kernel<float>", 3.0),
+                                      (3, "void pclb::step_strip_kernel<2, false>", 450.0),
+                                      (4, "void pclb::step_strip_kernel<2, true>", 50.0),
+                                      (5, "void pclb::ghost_kernel<float>", 3.0),
+                                      (6, "void pclb::step_strip_kernel<2, false>", 1450.0),
+                                      (7, "void pclb::step_strip_kernel<2, true>", 50.0),
+                                      (8, "__amd_rocclr_copyBuffer", 1048576.0)])
     rec = bench.summarize_counters(str(f), str(w), nodes=1000)
     e = rec["fp32"]
     assert e["fetch_bytes"] == pytest.approx(2000.0 * gib / 524288.0)
