@@ -101,7 +101,7 @@ __device__ inline float load_slot(const StripCtx& X, uint32_t soff, int qb, int 
 template <int K>
 __device__ inline void store_slot(const StripCtx& X, uint32_t soff, uint32_t voff, float v) {
   // the b32 builtins move raw 32-bit words: pass the float's bits
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), X.fout[K - 1], voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), X.fout[K - 1], voff, soff, STORE_NT);
 }
 
 __device__ inline uint32_t row_off(const StripCtx& X, int row, bool on) {

@@ -21,6 +21,10 @@ constexpr int NXCD = 8;   // accelerator dies; workgroups are dealt to them roun
 // last row and the halo loads of lanes that read no halo, so that none of them
 // needs a branch.
 constexpr uint32_t OOB = 0x80000000u;
+// Cache policy of the output stores: nontemporal (bit 1 on gfx950).  The new
+// state is not read again in this launch, so it should not displace the input
+// lines that the neighbouring strips still read as their azimuthal halo.
+constexpr int STORE_NT = 2;
 
 template <int V, int N, class Fn>
 __device__ inline void for_v(Fn&& fn) {
