@@ -161,6 +161,41 @@ def run_adjoint(W, torch, steps=200, ckpt=20):
                 fp32_vs_fp64_gradient=rel(g32, g64), finite_differences=fd)
 
 
+def adjoint_kernel_times(W, torch, steps=50):
+    """Adjoint step alone (ghost layers, ghost adjoint, node adjoint) against
+    the forward step, on one state of the 1024 x 2048 Richtmyer-Meshkov
+    recipe, with a seeded random cotangent; FP32 and FP64."""
+    from paper_1302_7104_amd.sim import Sim
+    res = {}
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    for prec in (32, 64):
+        P, F = W.richtmyer_meshkov(1024, 2048, 200)
+        sim = Sim(P, precision=prec)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        sim.step(5)
+        f = sim.state.clone()
+        lam = torch.randn(f.shape, generator=gen, device=f.device, dtype=f.dtype)
+        out = torch.empty_like(f)
+        for _ in range(5):
+            sim.adjoint_step(f, lam, out)
+        st = sim.stream
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            sim.adjoint_step(f, lam, out)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ta = e0.elapsed_time(e1) / steps
+        tf = time_steps(sim, torch, steps)
+        res[f"fp{prec}"] = {"adjoint_step_ms": ta, "forward_step_ms": tf, "ratio": ta / tf}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(W, target_s=25.0):
     """The FP64 CPU oracle, as it stands, on the same recipe at 512 x 1024
     (cost per cell-velocity update does not depend on the grid size)."""
@@ -252,6 +287,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true", help="headline FP32 step only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time the adjoint step alone against the forward step (1024 x 2048 "
+                         "Richtmyer-Meshkov) and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -274,6 +312,9 @@ def main():
     from paper_1302_7104_amd import workloads as W
     from paper_1302_7104_amd.sim import Sim
 
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_rm_1024x2048": adjoint_kernel_times(W, torch)}), flush=True)
+        return
     P, ms, diag = run_forward(W, Sim, torch, 32, args.steps, args.warmup)
     if args.calibrate_copy:
         calibrate_copy(torch)
