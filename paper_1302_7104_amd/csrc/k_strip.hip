@@ -39,6 +39,8 @@ using namespace strip;
 // addresses data stays below 2^31 (checked by strip_supported).
 struct StripCtx {
   __amdgpu_buffer_rsrc_t fin[NK], fout[NK], gh;
+  const float* fb;          // the input state (halo rows of uniform waves)
+  size_t plane;             // values per plane
   uint32_t plane_bytes;
   int nr, nth;
   int col;                  // this lane's column
@@ -133,16 +135,34 @@ __device__ inline void load_halo(const StripCtx& X, uint32_t soff, int row, bool
 
 // One output row i.  For every owned velocity the slots A, B, C hold three
 // consecutive rows in increasing order: (i-2, i-1, i) when the upwind side is
-// i-1 ("backward"), (i, i+1, i+2) otherwise.  After the velocity's terms are
-// computed, the lowest slot A is refilled with row (lowest + 3), and the
-// caller rotates the roles A <- B <- C <- A for the next row.
-template <int NSPLIT, int W, bool EDGE, bool UNI>
+// i-1 ("backward"), (i, i+1, i+2) otherwise; a ring of NS = 4 slots holds one
+// more row of look-ahead.  After the velocity's terms are computed, the lowest
+// slot A is refilled with row (lowest + NS), and the caller rotates the roles
+// by one slot for the next row.  A load is thus issued NS - 2 rows before the
+// row that first uses it.  more1: row i+1 is in the chunk (rest velocity,
+// halo); moreN: row i+NS-2 is (look-ahead rows).
+//
+// Azimuthal halo of uniform waves: lane v holds in (hlo, hhi) the two columns
+// beyond the strip on slot v's upwind side at row i; the pair for row i+1 is
+// read with one load for all slots at the start of the row (hp: lane v's
+// pointer to that pair in row 0), and each slot takes its pair with
+// readlane.  Mixed waves keep one pair of registers per slot (HA, HB).
+template <int NSPLIT, int W, bool EDGE, bool UNI, int NS>
 __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
-                                 const Roles<4 / NSPLIT>& RL, int i, bool more, const int* ta,
+                                 const Roles<4 / NSPLIT>& RL, int i, int ir, float rinv_lane,
+                                 bool more, bool moreN, const int* ta,
                                  float& r0, float* A, float* B, float* C, float* HA, float* HB,
-                                 double* lds) {
+                                 float& hlo, float& hhi, const float* hp, double* lds) {
   using O = Own<NSPLIT, W>;
   const int lane = threadIdx.x & 63;
+  float nlo = 0.0f, nhi = 0.0f;
+  if constexpr (UNI) {
+    if (more && lane < O::NV) {
+      const float2 t = *reinterpret_cast<const float2*>(hp + (size_t)(i + 1) * X.nth);
+      nlo = t.x;
+      nhi = t.y;
+    }
+  }
   // backward role of slot v: fixed in a uniform wave, per lane otherwise
   auto back = [&](int v) -> bool {
     if constexpr (UNI) return O::h_of(v) == 0;
@@ -185,13 +205,16 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   combine_partials(P, rho, ux, uy, E);
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
-  const float rinv = (float)T.rinv[i];
+  // 1/r of this row from lane (i - i_begin) of rinv_lane: a table load here
+  // would be waited for in order behind every look-ahead load and store in
+  // flight
+  const float rinv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rinv_lane), ir));
   const uint32_t ovoff = X.store ? (uint32_t)(i * X.nth) * 4u + X.col4 : OOB;
-  const uint32_t vb = row_off(X, i + 1, more), vf = row_off(X, i + 3, more);
-  if constexpr (W == 0) {            // rest velocity: relaxation only
+  const uint32_t vb = row_off(X, i + NS - 2, moreN), vf = row_off(X, i + NS, moreN);
+  if constexpr (W == 0) {            // rest velocity: relaxation only, one row ahead
     const float res = relax_rest<float>(ec, X.e, X.ome, (double)r0);
     store_slot<1>(X, 0, ovoff, res);
-    r0 = load_slot<EDGE, 1>(X, 0, 0, i + 1, vb, more);
+    r0 = load_slot<EDGE, 1>(X, 0, 0, i + 1, row_off(X, i + 1, more), more);
   }
   for_v<0, O::NV / 2>([&](auto pc) {
     constexpr int pk = decltype(pc)::value;     // (pair, k) index
@@ -218,7 +241,9 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
       if constexpr (UNI) {
         const bool tb = RL.tb[pl][h];
         const bool edge = tb ? X.edge_l : X.edge_r;
-        const float fix1 = tb ? HB[v] : HA[v], fix2 = tb ? HA[v] : HB[v];
+        const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hlo), v));
+        const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hhi), v));
+        const float fix1 = tb ? hi : lo, fix2 = tb ? lo : hi;
         const float z = lane_from(c, ta[v]);
         const float u1t = edge ? fix1 : z;
         d1t = c - u1t;
@@ -238,25 +263,35 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
       const float d1r = c - u1r, d2r = u1r - (bk ? A[v] : C[v]);
       const float res = mwb_update_d<float>(rl, aCr, Kr, d1r, d2r, aCt, Kt, d1t, d2t);
       store_slot<k>(X, RL.soff[pl][h], ovoff, res);
-      A[v] = load_slot<EDGE, k>(X, RL.soff[pl][h], RL.qb[pl][h], bk ? i + 1 : i + 3, bk ? vb : vf,
-                                more);
-      load_halo<k, UNI>(X, RL.soff[pl][h], i + 1, UNI ? RL.tb[pl][h] : false, more, HA[v], HB[v]);
+      A[v] = load_slot<EDGE, k>(X, RL.soff[pl][h], RL.qb[pl][h], bk ? i + NS - 2 : i + NS,
+                                bk ? vb : vf, moreN);
+      if constexpr (!UNI) load_halo<k, false>(X, RL.soff[pl][h], i + 1, false, more, HA[v], HB[v]);
     };
     one(std::integral_constant<int, v0>{}, b0, c0, rel[0]);
     one(std::integral_constant<int, v1>{}, b1, c1, rel[1]);
   });
+  if constexpr (UNI) {
+    hlo = nlo;
+    hhi = nhi;
+  }
 }
 
-template <int NSPLIT, int W, bool EDGE, bool UNI>
+template <int NSPLIT, int W, bool EDGE, bool UNI, int NS>
 __device__ inline void strip_march(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                    const Roles<4 / NSPLIT>& RL, int i_begin, int i_end,
                                    double* lds) {
   using O = Own<NSPLIT, W>;
-  float S0[O::NV], S1[O::NV], S2[O::NV];
-  float HA[O::NV], HB[O::NV];     // azimuthal halo of the current row, per slot
+  static_assert(NS == 3 || NS == 4, "ring of three or four rows");
+  float S[NS][O::NV];
+  float HA[UNI ? 1 : O::NV], HB[UNI ? 1 : O::NV];   // mixed waves: halo of the row, per slot
+  float hlo = 0.0f, hhi = 0.0f;                       // uniform waves: lane v holds slot v's pair
+  const float* hp = X.fb;
   // ds_bpermute byte address of the azimuthally upwind lane, per slot
   int ta[O::NV];
   const int lane = threadIdx.x & (WAVE - 1);
+  // 1/r of the chunk's rows, lane l holding row i_begin + l (chunks have at
+  // most 64 rows)
+  const float rinv_lane = i_begin + lane < X.nr ? (float)T.rinv[i_begin + lane] : 0.0f;
   float r0 = 0.0f;
   if constexpr (W == 0) r0 = load_slot<EDGE, 1>(X, 0, 0, i_begin, row_off(X, i_begin, true), true);
   for_v<0, O::NV>([&](auto vc) {
@@ -268,25 +303,59 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
     const bool bk = UNI ? h == 0 : ((G.rback >> d) & 1u);
     const int base = bk ? i_begin - 2 : i_begin;
     const uint32_t so = RL.soff[pl][h];
-    S0[v] = load_slot<EDGE, k>(X, so, qb, base, row_off(X, base, true), true);
-    S1[v] = load_slot<EDGE, k>(X, so, qb, base + 1, row_off(X, base + 1, true), true);
-    S2[v] = load_slot<EDGE, k>(X, so, qb, base + 2, row_off(X, base + 2, true), true);
-    load_halo<k, UNI>(X, so, i_begin, UNI ? RL.tb[pl][h] : false, true, HA[v], HB[v]);
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      // look-ahead slot sl >= 3 is first used at row i_begin + sl - 2
+      const bool on = sl < 3 || i_begin + sl - 2 < i_end;
+      S[sl][v] = load_slot<EDGE, k>(X, so, qb, base + sl, row_off(X, base + sl, on), on);
+    }
+    if constexpr (UNI) {
+      if (lane == v)
+        hp = X.fb + (size_t)(qb + ND * (k - 1)) * X.plane + (RL.tb[pl][h] ? X.hl4 : X.hr4) / 4u;
+    } else {
+      load_halo<k, false>(X, so, i_begin, false, true, HA[v], HB[v]);
+    }
   });
-  // one row per iteration; the ring rotates by register moves
-  for (int i = i_begin; i < i_end; ++i) {
-    strip_row<NSPLIT, W, EDGE, UNI>(T, X, G, RL, i, i + 1 < i_end, ta, r0, S0, S1, S2, HA, HB, lds);
-    for_v<0, O::NV>([&](auto vc) {
-      constexpr int v = decltype(vc)::value;
-      const float t = S0[v];
-      S0[v] = S1[v];
-      S1[v] = S2[v];
-      S2[v] = t;
-    });
+  if constexpr (UNI) {
+    if (lane < O::NV) {
+      const float2 t = *reinterpret_cast<const float2*>(hp + (size_t)i_begin * X.nth);
+      hlo = t.x;
+      hhi = t.y;
+    }
+  }
+  if constexpr (NS == 4) {
+    // four rows per iteration with the slot roles rotated at compile time, so
+    // the ring needs no register moves (a move of a register whose load is in
+    // flight would wait for that load and undo the look-ahead)
+    for (int i = i_begin; i < i_end; i += NS) {
+      for_v<0, NS>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        const int iu = i + u;
+        if (iu < i_end)
+          strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
+                                              iu + 1 < i_end, iu + NS - 2 < i_end, ta, r0, S[u % NS], S[(u + 1) % NS], S[(u + 2) % NS],
+                                              HA, HB, hlo, hhi, hp, lds);
+      });
+    }
+  } else {
+    // one row per iteration, the ring rotated by register moves (its loads
+    // are one row ahead and waited for at the next row's start anyway)
+    for (int i = i_begin; i < i_end; ++i) {
+      strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, i, i - i_begin, rinv_lane, i + 1 < i_end,
+                                          i + 1 < i_end, ta, r0,
+                                          S[0], S[1], S[2], HA, HB, hlo, hhi, hp, lds);
+      for_v<0, O::NV>([&](auto vc) {
+        constexpr int v = decltype(vc)::value;
+        const float t = S[0][v];
+        S[0][v] = S[1][v];
+        S[1][v] = S[2][v];
+        S[2][v] = t;
+      });
+    }
   }
 }
 
-template <int NSPLIT, int W, bool MIXED>
+template <int NSPLIT, int W, bool MIXED, int NS = MIXED ? 3 : 4>
 __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                   int i_begin, int i_end, double* lds) {
   using O = Own<NSPLIT, W>;
@@ -324,13 +393,13 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
   const bool all_uni = __syncthreads_and(uni ? 1 : 0) != 0;
   if (all_uni == MIXED) return;
   if constexpr (!MIXED) {
-    if (edge) strip_march<NSPLIT, W, true, true>(T, X, G, RL, i_begin, i_end, lds);
-    else strip_march<NSPLIT, W, false, true>(T, X, G, RL, i_begin, i_end, lds);
+    if (edge) strip_march<NSPLIT, W, true, true, NS>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, true, NS>(T, X, G, RL, i_begin, i_end, lds);
     return;
   }
   if (uni) {
-    if (edge) strip_march<NSPLIT, W, true, true>(T, X, G, RL, i_begin, i_end, lds);
-    else strip_march<NSPLIT, W, false, true>(T, X, G, RL, i_begin, i_end, lds);
+    if (edge) strip_march<NSPLIT, W, true, true, NS>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, true, NS>(T, X, G, RL, i_begin, i_end, lds);
   } else {
 #pragma unroll
     for (int pl = 0; pl < O::D4N; ++pl) {       // mixed: members in natural order
@@ -343,8 +412,8 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
         RL.tb[pl][h] = false;
       }
     }
-    if (edge) strip_march<NSPLIT, W, true, false>(T, X, G, RL, i_begin, i_end, lds);
-    else strip_march<NSPLIT, W, false, false>(T, X, G, RL, i_begin, i_end, lds);
+    if (edge) strip_march<NSPLIT, W, true, false, NS>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, false, NS>(T, X, G, RL, i_begin, i_end, lds);
   }
 }
 
@@ -373,6 +442,8 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
     X.fout[k - 1] = make_rsrc(out + ND * (k - 1) * plane);
   }
   X.gh = make_rsrc(ghost);
+  X.fb = f;
+  X.plane = plane;
   X.nr = nr;
   X.nth = nth;
   // column of this lane (periodic) and whether it stores an output
@@ -436,6 +507,7 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
                              const StripTune& tune, hipStream_t s) {
   if (!strip_supported<R>(T)) return hipErrorNotSupported;
   const int chunk_rows = tune.chunk > 0 ? tune.chunk : strip_default_chunk(T);
+  if (chunk_rows > WAVE) return hipErrorInvalidValue;   // 1/r of a chunk is held one row per lane
   const int split = tune.split > 0 ? tune.split : 2;
   const int order = tune.order >= 0 ? (tune.order ? 1 : 0) : 1;
   const int strips = n_strips(T.nth);
