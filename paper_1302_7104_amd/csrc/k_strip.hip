@@ -157,11 +157,12 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   const int lane = threadIdx.x & 63;
   float nlo = 0.0f, nhi = 0.0f;
   if constexpr (UNI) {
-    if (more && lane < O::NV) {
-      const float2 t = *reinterpret_cast<const float2*>(hp + (size_t)(i + 1) * X.nth);
-      nlo = t.x;
-      nhi = t.y;
-    }
+    // every lane loads (lanes past the slots read the first two values of a
+    // real row, which nobody uses), so that no branch splits the wave here
+    const int hrow = more ? i + 1 : i;
+    const float2 t = *reinterpret_cast<const float2*>(hp + (size_t)hrow * X.nth);
+    nlo = t.x;
+    nhi = t.y;
   }
   // backward role of slot v: fixed in a uniform wave, per lane otherwise
   auto back = [&](int v) -> bool {
@@ -294,49 +295,71 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
   const float rinv_lane = i_begin + lane < X.nr ? (float)T.rinv[i_begin + lane] : 0.0f;
   float r0 = 0.0f;
   if constexpr (W == 0) r0 = load_slot<EDGE, 1>(X, 0, 0, i_begin, row_off(X, i_begin, true), true);
+  if constexpr (UNI) {
+    // the first halo pair is loaded before the ring, so that at the loop's
+    // head it is as old as in later iterations (the compiler's wait counting
+    // merges both)
+    for_v<0, O::NV>([&](auto vc) {
+      constexpr int v = decltype(vc)::value;
+      constexpr int pl = O::pl_of(v), h = O::h_of(v), k = O::k_of_v(v);
+      if (lane == v)
+        hp = X.fb + (size_t)(RL.qb[pl][h] + ND * (k - 1)) * X.plane +
+             (RL.tb[pl][h] ? X.hl4 : X.hr4) / 4u;
+    });
+    const float2 t = *reinterpret_cast<const float2*>(hp + (size_t)i_begin * X.nth);
+    hlo = t.x;
+    hhi = t.y;
+  }
   for_v<0, O::NV>([&](auto vc) {
     constexpr int v = decltype(vc)::value;
     constexpr int pl = O::pl_of(v), h = O::h_of(v), k = O::k_of_v(v);
     const int qb = RL.qb[pl][h];
     const int d = qb - 1;                       // direction of the slot's velocity
     ta[v] = (((G.tback >> d) & 1u) ? lane - 1 : lane + 1) << 2;
-    const bool bk = UNI ? h == 0 : ((G.rback >> d) & 1u);
-    const int base = bk ? i_begin - 2 : i_begin;
-    const uint32_t so = RL.soff[pl][h];
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) {
-      // look-ahead slot sl >= 3 is first used at row i_begin + sl - 2
-      const bool on = sl < 3 || i_begin + sl - 2 < i_end;
-      S[sl][v] = load_slot<EDGE, k>(X, so, qb, base + sl, row_off(X, base + sl, on), on);
-    }
-    if constexpr (UNI) {
-      if (lane == v)
-        hp = X.fb + (size_t)(qb + ND * (k - 1)) * X.plane + (RL.tb[pl][h] ? X.hl4 : X.hr4) / 4u;
-    } else {
-      load_halo<k, false>(X, so, i_begin, false, true, HA[v], HB[v]);
-    }
+    if constexpr (!UNI) load_halo<k, false>(X, RL.soff[pl][h], i_begin, false, true, HA[v], HB[v]);
   });
-  if constexpr (UNI) {
-    if (lane < O::NV) {
-      const float2 t = *reinterpret_cast<const float2*>(hp + (size_t)i_begin * X.nth);
-      hlo = t.x;
-      hhi = t.y;
-    }
-  }
+  // the ring, one slot of every velocity after the other, so that the
+  // look-ahead slot is loaded last
+  for_v<0, NS>([&](auto sc) {
+    constexpr int sl = decltype(sc)::value;
+    // look-ahead slot sl >= 3 is first used at row i_begin + sl - 2
+    const bool on = sl < 3 || i_begin + sl - 2 < i_end;
+    for_v<0, O::NV>([&](auto vc) {
+      constexpr int v = decltype(vc)::value;
+      constexpr int pl = O::pl_of(v), h = O::h_of(v), k = O::k_of_v(v);
+      const int qb = RL.qb[pl][h];
+      const bool bk = UNI ? h == 0 : ((G.rback >> (qb - 1)) & 1u);
+      const int row = (bk ? i_begin - 2 : i_begin) + sl;
+      S[sl][v] = load_slot<EDGE, k>(X, RL.soff[pl][h], qb, row, row_off(X, row, on), on);
+    });
+  });
   if constexpr (NS == 4) {
     // four rows per iteration with the slot roles rotated at compile time, so
     // the ring needs no register moves (a move of a register whose load is in
     // flight would wait for that load and undo the look-ahead)
-    for (int i = i_begin; i < i_end; i += NS) {
+    // (whole groups of four rows run without a per-row condition, so that the
+    // compiler's wait counting sees every row's loads; the last rows of a
+    // chunk whose length is not a multiple of four follow with one)
+    int i = i_begin;
+    for (; i + NS <= i_end; i += NS) {
       for_v<0, NS>([&](auto uc) {
         constexpr int u = decltype(uc)::value;
         const int iu = i + u;
-        if (iu < i_end)
-          strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
-                                              iu + 1 < i_end, iu + NS - 2 < i_end, ta, r0, S[u % NS], S[(u + 1) % NS], S[(u + 2) % NS],
-                                              HA, HB, hlo, hhi, hp, lds);
+        strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
+                                            iu + 1 < i_end, iu + NS - 2 < i_end, ta, r0,
+                                            S[u % NS], S[(u + 1) % NS], S[(u + 2) % NS], HA, HB,
+                                            hlo, hhi, hp, lds);
       });
     }
+    for_v<0, NS - 1>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const int iu = i + u;
+      if (iu < i_end)
+        strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
+                                            iu + 1 < i_end, iu + NS - 2 < i_end, ta, r0,
+                                            S[u % NS], S[(u + 1) % NS], S[(u + 2) % NS], HA, HB,
+                                            hlo, hhi, hp, lds);
+    });
   } else {
     // one row per iteration, the ring rotated by register moves (its loads
     // are one row ahead and waited for at the next row's start anyway)
