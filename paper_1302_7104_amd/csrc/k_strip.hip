@@ -2,11 +2,13 @@
 // storage.  A workgroup owns a strip of 64 consecutive theta columns (one per
 // lane, the strip aligned to 64 columns so that every load and store covers
 // whole cache lines) and marches in r over a chunk of rows.  For each velocity
-// a wavefront keeps the three rows its radial MWB stencil needs (centre and
-// the two upwind neighbours) in registers, so every f value of the chunk is
-// read from HBM once.  The azimuthal neighbours come from the adjacent lanes
-// (ds_bpermute); the two columns beyond the strip on the upwind side are read
-// per row by the edge lane (one 8-byte load per velocity).
+// a wavefront keeps in registers the three rows its radial MWB stencil needs
+// (centre and the two upwind neighbours) and one row of look-ahead, so every
+// f value of the chunk is read from HBM once and every load is issued two
+// rows before its first use.  The azimuthal neighbours come from the adjacent
+// lanes (ds_bpermute); the two columns beyond the strip on the upwind side
+// are read per row for all velocities of a wave with one load (lane v holds
+// velocity v's pair).
 //
 // Per row: moments, equilibrium and analytic relaxation in double (Eqs.
 // moment1-3, F_k, feq, operator1_new), the radial and azimuthal MWB terms in
