@@ -65,9 +65,9 @@ enum {
  * n_theta >= 64 and 9 * 4 * n_r * n_theta < 2^31 bytes; elsewhere the node
  * kernel runs whatever is asked.  Its launch shape can be overridden, for
  * tuning only, with the environment variables PCLB_STRIP_CHUNK (rows per
- * workgroup), PCLB_STRIP_SPLIT (1, 2 or 4 wavefronts per strip) and
+ * workgroup, 1 to 64), PCLB_STRIP_SPLIT (1, 2 or 4 wavefronts per strip) and
  * PCLB_STRIP_ORDER (1 XCD-contiguous workgroup order, 0 plain), read by
- * pclb_create. */
+ * pclb_create, which returns PCLB_EINVAL for values out of range. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */

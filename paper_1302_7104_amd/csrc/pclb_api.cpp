@@ -120,6 +120,13 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   if (const char* v = std::getenv("PCLB_STRIP_CHUNK")) c->tune.chunk = std::atoi(v);
   if (const char* v = std::getenv("PCLB_STRIP_SPLIT")) c->tune.split = std::atoi(v);
   if (const char* v = std::getenv("PCLB_STRIP_ORDER")) c->tune.order = std::atoi(v);
+  if (c->tune.chunk < 0 || c->tune.chunk > 64 || c->tune.split < 0 || c->tune.split == 3 ||
+      c->tune.split > 4 || c->tune.order > 1) {
+    delete c;
+    return fail(nullptr, PCLB_EINVAL,
+                "strip launch shape out of range (PCLB_STRIP_CHUNK 1-64, PCLB_STRIP_SPLIT 1, 2 "
+                "or 4, PCLB_STRIP_ORDER 0 or 1)");
+  }
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return fail(nullptr, PCLB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
   const int nr = cfg->n_r, nth = cfg->n_theta;

@@ -55,3 +55,18 @@ def test_create_rejects_invalid_config(kw, code):
     assert rc == code
     assert not ctx.value
     assert L.pclb_last_error(None)
+
+
+@pytest.mark.parametrize("var,val", [("PCLB_STRIP_CHUNK", "65"), ("PCLB_STRIP_CHUNK", "-1"),
+                                     ("PCLB_STRIP_SPLIT", "3"), ("PCLB_STRIP_ORDER", "2")])
+def test_create_rejects_strip_shape_out_of_range(var, val, monkeypatch):
+    """The strip kernel holds 1/r of a chunk one row per lane: more than 64
+    rows per chunk (or an unknown split or order) is refused at creation,
+    before any device call."""
+    monkeypatch.setenv(var, val)
+    L = N.lib()
+    ctx = ctypes.c_void_p()
+    rc = L.pclb_create(ctypes.byref(cfg()), ctypes.byref(ctx))
+    assert rc == -1
+    assert not ctx.value
+    assert b"launch shape" in L.pclb_last_error(None)

@@ -252,7 +252,8 @@ def test_strip_launch_shapes_bitwise_equal_node_kernel(shape, monkeypatch):
     """The FP32 strip kernel in every launch shape (wavefronts per strip,
     rows per chunk, workgroup order) equals the node kernel bit for bit:
     ragged last strips, odd N_theta (halo pairs not adjacent), a single strip,
-    strips with and without sign changes inside, chunks of 1 to 7 rows."""
+    strips with and without sign changes inside, chunks of 1 to 7 rows and of
+    64 (the longest), whole groups of four rows and every tail length."""
     from paper_1302_7104_amd import _native as N
     nr, nth = shape
     P, F = W.kelvin_helmholtz(nr, nth, 6)
@@ -261,7 +262,8 @@ def test_strip_launch_shapes_bitwise_equal_node_kernel(shape, monkeypatch):
     s.step(6)
     want = s.state.cpu().numpy()
     s.close()
-    for split, chunk, order in [(1, 0, 1), (2, 0, 1), (4, 0, 1), (2, 7, 0), (2, 1, 1), (4, 3, 0)]:
+    for split, chunk, order in [(1, 0, 1), (2, 0, 1), (4, 0, 1), (2, 7, 0), (2, 1, 1), (4, 3, 0),
+                                (2, 64, 1), (2, 5, 1), (2, 6, 0)]:
         monkeypatch.setenv("PCLB_STRIP_SPLIT", str(split))
         monkeypatch.setenv("PCLB_STRIP_CHUNK", str(chunk))
         monkeypatch.setenv("PCLB_STRIP_ORDER", str(order))
