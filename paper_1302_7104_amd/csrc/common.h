@@ -323,10 +323,11 @@ PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, 
 // Combined-scheme update of one node (Eq. combined_scheme): centre values fc,
 // radial neighbours row(q, di) at rows i+di (di = -2, -1, 1, 2; ghost rows
 // included) and azimuthal neighbours col(q, dj) at columns j+dj of row i.
-// res receives f at t + dt.
-template <class R, class RowFn, class ColFn>
-PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, const R* fc, RowFn row,
-                                ColFn col, R* res) {
+// put(q, value) receives f_q at t + dt as soon as it is computed (so that a
+// kernel can store it at once instead of holding all 33 results).
+template <class R, class RowFn, class ColFn, class PutFn>
+PCLB_HD inline void node_update_put(const Tables& T, int i, double ct, double st, const R* fc,
+                                    RowFn row, ColFn col, PutFn put) {
   double fd[NQ];
   for (int q = 0; q < NQ; ++q) fd[q] = (double)fc[q];
   double rho, ux, uy, E;
@@ -334,7 +335,7 @@ PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, co
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
   const double e = T.e, ome = 1.0 - T.e;
-  res[0] = relax_rest<R>(ec, e, ome, fd[0]);       // rest velocity: no convection
+  put(0, relax_rest<R>(ec, e, ome, fd[0]));       // rest velocity: no convection
   DirGeom<R> G;
   dir_geometry(ct, st, T.dt_dr, T.dt_dth, G);
   const R rinv = (R)T.rinv[i];
@@ -356,11 +357,18 @@ PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, co
         const int q = qidx(k, d);
         const int sr = ((G.rback >> d) & 1u) ? -1 : 1;   // upwind offset in r
         const int sc = ((G.tback >> d) & 1u) ? -1 : 1;   // upwind offset in theta
-        res[q] = mwb_update<R>(rel[h], fc[q], aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt,
-                               col(q, sc), col(q, 2 * sc));
+        put(q, mwb_update<R>(rel[h], fc[q], aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt,
+                             col(q, sc), col(q, 2 * sc)));
       }
     }
   }
+}
+
+// The same with the results in res[0..NQ-1].
+template <class R, class RowFn, class ColFn>
+PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, const R* fc, RowFn row,
+                                ColFn col, R* res) {
+  node_update_put<R>(T, i, ct, st, fc, row, col, [&](int q, R v) { res[q] = v; });
 }
 
 // Ghost layers of one wall and column (Sec. II.C, radial boundary condition):

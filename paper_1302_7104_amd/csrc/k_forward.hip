@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) step_node_kernel(Tables T, const R* __res
   const int nr = T.nr, nth = T.nth;
   const size_t plane = (size_t)nr * nth;
   const size_t c0 = (size_t)i * nth + j;
-  R fc[NQ], res[NQ];
+  R fc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) fc[q] = f[q * plane + c0];
   auto row = [&](int q, int di) { return fetch(f, ghost, q, i + di, j, nr, nth, plane); };
@@ -65,9 +65,11 @@ __global__ void __launch_bounds__(256) step_node_kernel(Tables T, const R* __res
     t = t < 0 ? t + nth : (t >= nth ? t - nth : t);
     return f[q * plane + (size_t)i * nth + t];
   };
-  node_update<R>(T, i, T.cth[j], T.sth[j], fc, row, col, res);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) out[q * plane + c0] = res[q];
+  // each result is stored as soon as it is computed: holding all 33 (with the
+  // centre values and the neighbours in flight) kept the kernel at one wave
+  // per SIMD
+  node_update_put<R>(T, i, T.cth[j], T.sth[j], fc, row, col,
+                     [&](int q, R v) { out[q * plane + c0] = v; });
 }
 
 // ---------------------------------------------------------------------------
