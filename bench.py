@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true", help="headline FP32 step only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="time the FP64 step (node kernel) on the same workload and exit")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time the adjoint step alone against the forward step (1024 x 2048 "
                          "Richtmyer-Meshkov) and exit")
@@ -312,6 +314,15 @@ def main():
     from paper_1302_7104_amd import workloads as W
     from paper_1302_7104_amd.sim import Sim
 
+    if args.fp64_only:
+        P64, ms64, _ = run_forward(W, Sim, torch, 64, args.steps, args.warmup)
+        nodes = P64.nr * P64.nth
+        print(json.dumps({"workload": "kelvin_helmholtz_4096x8192", "precision": 64,
+                          "ms_per_step": ms64,
+                          "gcellvel_per_s": NQ * nodes / (ms64 * 1e-3) / 1e9,
+                          "hbm_frac": 2 * NQ * nodes * 8 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS}),
+              flush=True)
+        return
     if args.adjoint_only:
         print(json.dumps({"adjoint_rm_1024x2048": adjoint_kernel_times(W, torch)}), flush=True)
         return
