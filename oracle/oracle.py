@@ -92,16 +92,16 @@ def lib():
         L.or_relax_node.argtypes = [_D, ctypes.c_double, ctypes.c_double, _D]
         L.or_mwb_term.argtypes = [ctypes.c_double, _D, ctypes.c_int32]
         L.or_mwb_term.restype = ctypes.c_double
-        L.or_mwb_grad.argtypes = [ctypes.c_double, _D, _D]
-        L.or_set_kink.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.or_set_tie.argtypes = [ctypes.c_double]
+        L.or_mwb_term_eta.argtypes = [ctypes.c_double, _D]
+        L.or_mwb_term_eta.restype = ctypes.c_double
+        L.or_mwb_grad.argtypes = [ctypes.c_double, _D, ctypes.c_double, _D]
         L.or_step.argtypes = [G, _D, _D, ctypes.c_int32]
         L.or_step.restype = ctypes.c_int
         L.or_step_sample.argtypes = [G, _D, _I, ctypes.c_int32, _D]
         L.or_init_feq.argtypes = [G, _D, _D, _D, _D, _D]
         L.or_fields.argtypes = [G, _D, _D, _D, _D, _D]
         L.or_diagnostics.argtypes = [G, _D, _D]
-        L.or_adjoint_step.argtypes = [G, _D, _D, _D]
+        L.or_adjoint_step.argtypes = [G, _D, _D, ctypes.c_double, _D]
         L.or_adjoint_init.argtypes = [G, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_threads.argtypes = [ctypes.c_int32]
@@ -153,28 +153,30 @@ def relax_node(f33, dt, tau) -> np.ndarray:
     return out
 
 
+#: tie threshold of the adjoint for states computed in double precision
+TIE_FP64 = 1e-13
+
+
 def mwb_term(C, psi5, s_mode: int = 0) -> float:
-    """Eq. MWB Scheme: the convection term for psi_{j-2..j+2} at Courant number C.
-    s_mode=1 sets S = 0 (Warming-Beam)."""
+    """Eq. MWB Scheme (division-free form of the switch): the convection term
+    for psi_{j-2..j+2} at Courant number C.  s_mode=1 sets S = 0 (Warming-Beam)."""
     psi5 = _f64(psi5)
     return lib().or_mwb_term(float(C), _p(psi5), int(s_mode))
 
 
-def mwb_grad(C, psi5) -> np.ndarray:
+def mwb_term_eta(C, psi5) -> float:
+    """The same term with eta and S(eta) as printed (0 when delta = 0)."""
+    psi5 = _f64(psi5)
+    return lib().or_mwb_term_eta(float(C), _p(psi5))
+
+
+def mwb_grad(C, psi5, tie_eps: float = TIE_FP64) -> np.ndarray:
+    """d(mwb_term)/d(psi_{j-2..j+2}) with the derivative convention at the
+    kinks: differences within tie_eps x the stencil magnitude count as zero,
+    sgn(0) = 0, and (1, 0) where both upwind differences vanish."""
     psi5 = _f64(psi5); g = np.zeros(5)
-    lib().or_mwb_grad(float(C), _p(psi5), _p(g))
+    lib().or_mwb_grad(float(C), _p(psi5), float(tie_eps), _p(g))
     return g
-
-
-def set_kink(h1: float, h2: float) -> None:
-    """(dh/d(delta), dh/d(delta')) used by the adjoint where delta = delta' = 0."""
-    lib().or_set_kink(float(h1), float(h2))
-
-
-def set_tie(eps: float) -> None:
-    """Relative size below which an upwind difference counts as zero when the
-    adjoint picks its derivative branch (1e-13 by default)."""
-    lib().or_set_tie(float(eps))
 
 
 def step(grid: Grid, f: np.ndarray, nsteps: int) -> tuple[np.ndarray, int]:
@@ -224,12 +226,14 @@ def diagnostics(grid: Grid, f: np.ndarray) -> np.ndarray:
     return out
 
 
-def adjoint_step(grid: Grid, f_t: np.ndarray, lam_next: np.ndarray) -> np.ndarray:
-    """lam_t = (dPhi/df at f_t)^T lam_next for one combined-scheme step."""
+def adjoint_step(grid: Grid, f_t: np.ndarray, lam_next: np.ndarray,
+                 tie_eps: float = TIE_FP64) -> np.ndarray:
+    """lam_t = (dPhi/df at f_t)^T lam_next for one combined-scheme step, with
+    the derivative convention of ``mwb_grad`` at the switch's kinks."""
     f_t = _f64(f_t); lam_next = _f64(lam_next)
     out = np.empty_like(f_t)
     g = grid.c()
-    lib().or_adjoint_step(ctypes.byref(g), _p(f_t), _p(lam_next), _p(out))
+    lib().or_adjoint_step(ctypes.byref(g), _p(f_t), _p(lam_next), float(tie_eps), _p(out))
     return out
 
 

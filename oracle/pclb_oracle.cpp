@@ -30,8 +30,9 @@
 //  * nodes r_i = R1 + i dr (i = 0..nr-1, dr = (R2-R1)/(nr-1)) and
 //    theta_j = (j+1) dtheta (dtheta = 2 pi / nth);
 //  * the combined scheme evaluates all three terms from f at time t;
-//  * the MWB bracket uses (1 - |C|); when the upwind difference delta is zero
-//    the whole convection term is zero (its limit), and C = 0 counts as C >= 0;
+//  * the MWB bracket uses (1 - |C|) and is evaluated in the division-free form
+//    of the switch, which is 0 when both upwind differences vanish; C = 0
+//    counts as C >= 0;
 //  * radial ghost nodes hold the equilibrium of linearly extrapolated density
 //    and temperature; the velocity there is set per boundary kind.
 
@@ -186,41 +187,71 @@ template <class T> void macros_of_M(const T M[4], T& rho, T& ux, T& uy, T& E) {
   E = M[3] / rho - 0.5 * (ux * ux + uy * uy);
 }
 
-// Sec. II.B, Eqs. WB_Scheme_2 / MWB Scheme with delta and eta as defined there,
-// and S(eta) = (|eta| - 1)/(|eta| + 1).  psi holds psi_{j-2..j+2}.  Returns the
-// convection term [C + (1/2) C (1-|C|)(1-S(eta))(1-eta)] delta that the scheme
-// subtracts.  s_mode = 1 replaces S by 0 (the plain Warming-Beam form).
+// Sec. II.B, Eqs. WB_Scheme_2 / MWB Scheme.  With the upwind difference
+// delta (backward when C >= 0, forward otherwise), the next one upwind
+// delta' = eta delta, and S(eta) = (|eta| - 1)/(|eta| + 1), the scheme
+// subtracts [C + (1/2) C (1-|C|)(1-S(eta))(1-eta)] delta.  Since
+//   (1/2)(1 - S(eta))(1 - eta) delta = (delta - delta') |delta| / (|delta| + |delta'|)
+// for every delta != 0, the term is evaluated in that division-free form, with
+// the ratio taken as 0 when |delta| + |delta'| = 0 (the limit delta -> 0 of the
+// eta-form, whose whole bracket then multiplies a vanishing delta).  This is
+// the one canonical form of the switch: the eta-form loses digits in
+// 1 - S(eta) when |eta| >> 1.  psi holds psi_{j-2..j+2}.  s_mode = 1 replaces
+// S by 0, which turns the bracket into the plain Warming-Beam one:
+// C delta + (1/2) C (1-|C|)(delta - delta').
+template <class T> void upwind_differences(double C, const T psi[5], T& delta, T& dprime) {
+  if (C >= 0) { delta = psi[2] - psi[1]; dprime = psi[1] - psi[0]; }
+  else        { delta = psi[3] - psi[2]; dprime = psi[4] - psi[3]; }
+}
+
 template <class T> T mwb_term(double C, const T psi[5], int s_mode) {
-  T delta, num;
-  if (C >= 0) { delta = psi[2] - psi[1]; num = psi[1] - psi[0]; }
-  else        { delta = psi[3] - psi[2]; num = psi[4] - psi[3]; }
-  if (val(delta) == 0.0) return T(0.0);
-  T eta = num / delta;
-  T S = s_mode ? T(0.0) : (dabs(eta) - 1.0) / (dabs(eta) + 1.0);
+  T delta, dprime;
+  upwind_differences(C, psi, delta, dprime);
+  const double K = C * (1.0 - std::fabs(C));
+  if (s_mode) return C * delta + 0.5 * K * (delta - dprime);
+  T den = dabs(delta) + dabs(dprime);
+  if (val(den) == 0.0) return T(0.0);
+  return C * delta + K * ((delta - dprime) * dabs(delta) / den);
+}
+
+// The same term written with eta and S(eta) exactly as printed (0 when
+// delta = 0).  Kept only to pin the division-free form against the printed one.
+double mwb_term_eta(double C, const double psi[5]) {
+  double delta, dprime;
+  upwind_differences(C, psi, delta, dprime);
+  if (delta == 0.0) return 0.0;
+  double eta = dprime / delta;
+  double S = (std::fabs(eta) - 1.0) / (std::fabs(eta) + 1.0);
   return (C + 0.5 * C * (1.0 - std::fabs(C)) * (1.0 - S) * (1.0 - eta)) * delta;
 }
 
 // Partial derivatives of mwb_term with respect to psi_{j-2..j+2}, written as
-// derivatives of the term in (delta, delta') mapped back to the stencil.  The
-// term is not differentiable where delta or delta' vanishes, and there the
-// derivative branch would be decided by rounding noise; so a difference whose
-// size is within TIE_EPS times the stencil's magnitude counts as zero.  With
-// delta = 0 the term is C delta + C(1-|C|) h, h = (delta - delta') |delta| /
-// (|delta| + |delta'|): dh/d(delta) = dh/d(delta') = 0 when delta' != 0, and
-// (dh/d(delta), dh/d(delta')) = KINK_H when delta' = 0 too.  Elsewhere the
-// derivatives come from forward-mode differentiation of the term in the
-// division-free form of h (sgn(0) = 0 inside |.|).
-double KINK_H[2] = {1.0, 0.0};
-double TIE_EPS = 1e-13;
+// derivatives of the term in (delta, delta') mapped back to the stencil.
+//
+// The term is not differentiable where delta or delta' vanishes.  The
+// derivative convention (a reading: the paper has no adjoint):
+//  * a difference whose size is at most tie_eps times the stencil's magnitude
+//    |psi| summed over its three nodes counts as exactly zero, so that the
+//    rounding of the state does not pick the branch (the caller passes the
+//    threshold that suits the precision the state was computed in);
+//  * sgn(0) = 0 inside |.|; with delta = 0 and delta' != 0 this gives
+//    dh/d(delta) = dh/d(delta') = 0 for h = (delta - delta')|delta|/(|delta| + |delta'|),
+//    the mean of the two one-sided derivatives (what a central difference
+//    across the kink sees);
+//  * with delta = delta' = 0, (dh/d(delta), dh/d(delta')) = (1, 0), the exact
+//    one-sided derivative for a perturbation of any single stencil node.
+// Elsewhere the derivatives come from forward-mode differentiation of the
+// division-free form.
+constexpr double KINK_H[2] = {1.0, 0.0};
 
-void mwb_grad(double C, const double psi[5], double g[5]) {
+void mwb_grad(double C, const double psi[5], double tie_eps, double g[5]) {
   for (int n = 0; n < 5; ++n) g[n] = 0;
   const bool back = C >= 0;
-  double delta = back ? psi[2] - psi[1] : psi[3] - psi[2];
-  double dprime = back ? psi[1] - psi[0] : psi[4] - psi[3];
+  double delta, dprime;
+  upwind_differences(C, psi, delta, dprime);
   double mag = back ? std::fabs(psi[0]) + std::fabs(psi[1]) + std::fabs(psi[2])
                     : std::fabs(psi[2]) + std::fabs(psi[3]) + std::fabs(psi[4]);
-  double thr = TIE_EPS * mag;
+  double thr = tie_eps * mag;
   if (std::fabs(delta) <= thr) delta = 0.0;
   if (std::fabs(dprime) <= thr) dprime = 0.0;
   double K = C * (1.0 - std::fabs(C));
@@ -230,11 +261,6 @@ void mwb_grad(double C, const double psi[5], double g[5]) {
     dd = C + K * h1;
     ddp = K * h2;
   } else {
-    // The term differentiated through the identity
-    //   (1/2)(1 - S(eta))(1 - eta) delta = (delta - delta') |delta| / (|delta| + |delta'|),
-    // the same function written without 1 - S(eta), which cancels to a few
-    // digits when |eta| >> 1 (a difference just above the tie threshold next
-    // to a large one).
     Dual<2> D(delta), Dp(dprime);
     D.d[0] = 1.0;
     Dp.d[1] = 1.0;
@@ -433,13 +459,11 @@ double or_mwb_term(double C, const double* psi, int32_t s_mode) {
   return mwb_term<double>(C, psi, s_mode);
 }
 
-void or_mwb_grad(double C, const double* psi, double* g) { mwb_grad(C, psi, g); }
+double or_mwb_term_eta(double C, const double* psi) { return mwb_term_eta(C, psi); }
 
-// Choice of (dh/d(delta), dh/d(delta')) where both upwind differences vanish.
-void or_set_kink(double h1, double h2) { KINK_H[0] = h1; KINK_H[1] = h2; }
-
-// Relative size below which an upwind difference counts as zero in the adjoint.
-void or_set_tie(double eps) { TIE_EPS = eps; }
+void or_mwb_grad(double C, const double* psi, double tie_eps, double* g) {
+  mwb_grad(C, psi, tie_eps, g);
+}
 
 
 // Eq. combined_scheme applied nsteps times: f_out = f after nsteps steps.
@@ -619,8 +643,11 @@ void or_diagnostics(const OrGrid* gp, const double* f, double* out) {
 // where Phi is the combined-scheme step of or_step (with terms = 7), including
 // the dependence of the radial ghost nodes on the two real rows next to each
 // wall.  Reverse-mode, written as a scatter from each output node to the inputs
-// it depends on.
-void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next, double* lam_out) {
+// it depends on.  tie_eps is the relative size below which an upwind
+// difference counts as zero (the derivative convention of mwb_grad): 1e-13
+// suits a state computed in double precision.
+void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next, double tie_eps,
+                     double* lam_out) {
   const OrGrid& g = *gp;
   Geometry geo(g);
   size_t tot = (size_t)NQ * g.nr * g.nth, n = (size_t)g.nr * g.nth;
@@ -675,7 +702,7 @@ void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next
         double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
         double psi[5], gr[5];
         for (int s = 0; s < 5; ++s) psi[s] = P.at(q, i - 2 + s, j);
-        mwb_grad(Cr, psi, gr);
+        mwb_grad(Cr, psi, tie_eps, gr);
         for (int s = 0; s < 5; ++s) {
           int ii = i - 2 + s;
           double v = -lam * gr[s];
@@ -687,7 +714,7 @@ void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next
           }
         }
         for (int s = 0; s < 5; ++s) psi[s] = P.at(q, i, j - 2 + s);
-        mwb_grad(Ct, psi, gr);
+        mwb_grad(Ct, psi, tie_eps, gr);
         for (int s = 0; s < 5; ++s) {
           int jj = ((j - 2 + s) % g.nth + g.nth) % g.nth;   // periodic wrap
           lam_out[idx(g, q, i, jj)] += -lam * gr[s];

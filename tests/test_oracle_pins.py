@@ -203,7 +203,9 @@ def test_mwb_with_S_zero_is_warming_beam():
 
 
 def test_mwb_switch_equals_division_free_form():
-    # (1/2)(1 - S(eta))(1 - eta) delta = (delta - delta')|delta|/(|delta|+|delta'|)
+    # The oracle evaluates the switch in the division-free form
+    #   (1/2)(1 - S(eta))(1 - eta) delta = (delta - delta')|delta|/(|delta|+|delta'|);
+    # away from cancellation it equals the printed eta-form to rounding.
     for _ in range(2000):
         C = RNG.uniform(-1, 1)
         p = RNG.normal(size=5)
@@ -211,8 +213,42 @@ def test_mwb_switch_equals_division_free_form():
             d, dp = p[2] - p[1], p[1] - p[0]
         else:
             d, dp = p[3] - p[2], p[4] - p[3]
-        alt = C * d + C * (1 - abs(C)) * (d - dp) * abs(d) / (abs(d) + abs(dp))
-        assert abs(O.mwb_term(C, p) - alt) <= 1e-13 * (abs(d) + abs(dp))
+        assert abs(O.mwb_term(C, p) - O.mwb_term_eta(C, p)) <= 1e-13 * (abs(d) + abs(dp))
+
+
+def test_mwb_division_free_form_is_the_exact_eta_form():
+    # Where |eta| >> 1 the printed form cancels in 1 - S(eta) in floating point
+    # (an error of about one ulp of |delta'|, large against the term itself,
+    # which is of the size of |delta|); the division-free form agrees with the
+    # printed formula evaluated at 50 digits on the very same stencil values,
+    # to a few ulps of the term.
+    import mpmath as mp
+    mp.mp.dps = 50
+    rng = np.random.default_rng(77)
+    worst_eta, worst_free = 0.0, 0.0
+    for _ in range(400):
+        C = rng.uniform(-1, 1)
+        c = rng.uniform(0.5, 1.5)
+        d = rng.choice([-1, 1]) * 10.0 ** rng.uniform(-12, 0)
+        dp = rng.choice([-1, 1]) * 10.0 ** rng.uniform(-12, 0)
+        if C >= 0:
+            p = np.array([c - d - dp, c - d, c, 0.3, 0.2])
+        else:
+            p = np.array([0.3, 0.2, c, c + d, c + d + dp])
+        P = [mp.mpf(float(x)) for x in p]
+        Cm = mp.mpf(C)
+        dm, dpm = (P[2] - P[1], P[1] - P[0]) if C >= 0 else (P[3] - P[2], P[4] - P[3])
+        eta = dpm / dm
+        S = (abs(eta) - 1) / (abs(eta) + 1)
+        lin = Cm * dm
+        lim = Cm * (1 - abs(Cm)) * (1 - S) * (1 - eta) / 2 * dm
+        exact = float(lin + lim)
+        scale = float(abs(lin) + abs(lim))
+        worst_free = max(worst_free, abs(O.mwb_term(C, p) - exact) / scale)
+        worst_eta = max(worst_eta, abs(O.mwb_term_eta(C, p) - exact) / scale)
+    assert worst_free <= 1e-15, worst_free
+    # the printed form, evaluated as printed, is the one that loses digits
+    assert worst_eta > 1e3 * worst_free, (worst_eta, worst_free)
 
 
 def test_mwb_monotone_bound():
@@ -281,6 +317,60 @@ def test_mwb_grad_kinks():
         fd = (O.mwb_term(C, p + e) - O.mwb_term(C, p)) / 1e-7
         assert abs(fd - want) < 1e-8
         assert abs(g[n] - want) < 1e-15
+
+
+@pytest.mark.parametrize("C", [0.37, -0.62])
+def test_mwb_grad_tie_rule_matches_finite_differences(C):
+    """The tie rule of the adjoint, pinned to the term itself.  A stencil whose
+    upwind difference delta is within tie_eps x |stencil| of zero gets the
+    derivative at delta = 0 with sgn(0) = 0: the mean of the two one-sided
+    derivatives, which is what a central difference straddling the kink
+    returns, while one-sided difference quotients taken from the kink return
+    the two one-sided slopes C +- K.  Outside the threshold the ordinary
+    derivative of the side the stencil lies on is returned."""
+    K = C * (1 - abs(C))
+    tie = 1e-5
+    c, dp = 0.8, 0.05                      # delta' != 0
+    for tiny in (0.0, 3e-7, -2e-7, 1e-3, -1e-3):
+        # stencil with upwind differences (delta, delta') = (tiny, dp); the
+        # centre value is node 2, delta = sgn * (psi_c - psi_u1)
+        if C >= 0:
+            p = np.array([c - tiny - dp, c - tiny, c, 0.4, 0.9])
+            n_u1, sgn = 1, 1.0
+        else:
+            p = np.array([0.9, 0.4, c, c - tiny, c - tiny - dp])
+            n_u1, sgn = 3, -1.0
+        d_true = p[2] - p[1] if C >= 0 else p[3] - p[2]
+        mag = np.abs(p[0:3]).sum() if C >= 0 else np.abs(p[2:5]).sum()
+        tied = abs(d_true) <= tie * mag
+        assert tied == (abs(tiny) < 1e-6)
+        g = O.mwb_grad(C, p, tie_eps=tie)
+
+        def T(x):
+            q = p.copy(); q[2] = x
+            return O.mwb_term(C, q)
+
+        # d T / d psi_c at delta = 0 from either side: (C + K dh/d(delta)) x
+        # d(delta)/d(psi_c) with d(delta)/d(psi_c) = sgn and dh/d(delta) =
+        # -sgn(delta') for delta > 0, +sgn(delta') for delta < 0
+        one_sided = sorted([sgn * (C + K), sgn * (C - K)])
+        if tied:
+            mean = 0.5 * (one_sided[0] + one_sided[1])
+            assert abs(g[2] - mean) < 1e-15
+            h = 1e-4
+            central = (T(p[2] + h) - T(p[2] - h)) / (2 * h)
+            assert abs(g[2] - central) < 1e-2 * abs(K), (tiny, g[2], central)
+            # from the kink itself each one-sided quotient is one of the slopes
+            x0 = p[2] - sgn * d_true           # psi_c with delta exactly 0
+            right = (T(x0 + h) - T(x0)) / h
+            left = (T(x0) - T(x0 - h)) / h
+            assert sorted([left, right]) == pytest.approx(one_sided, abs=1e-2 * abs(K))
+            # delta depends on psi_u1 with the opposite sign
+            assert abs(g[n_u1] + g[2]) < 1e-15
+        else:
+            eps = 1e-9
+            side = (T(p[2] + eps) - T(p[2] - eps)) / (2 * eps)
+            assert abs(g[2] - side) < 1e-6 * (1 + abs(side)), (tiny, g[2], side)
 
 
 def test_mwb_grad_large_eta_matches_high_precision():
@@ -576,3 +666,80 @@ def test_step_sample_matches_full_step():
     s = O.step_sample(g, f0, nodes)
     for n, (i, j) in enumerate(nodes):
         np.testing.assert_array_equal(s[n], full[:, i, j])
+
+
+# --------------------------------------------------------------------------
+# Counts the oracle reports, pinned on constructed states.
+
+def test_diagnostics_nonfinite_count_and_exclusion():
+    """A uniform state with NaN or infinite values planted at a known set of
+    nodes (several velocities at some of them): the non-finite count is the
+    number of distinct nodes, and the totals cover exactly the other nodes,
+    whose mass is known in closed form."""
+    P, F = W.uniform(12, 40, r1=1.0, r2=2.0, rho=1.3, T=0.9)
+    g = grid_of(P)
+    f = O.init_feq(g, **F)
+    bad_nodes = [(0, 0), (3, 7), (3, 8), (11, 39), (6, 20)]
+    f[5, 0, 0] = np.nan
+    f[0, 3, 7] = np.inf
+    f[12, 3, 7] = np.nan
+    f[32, 3, 8] = -np.inf
+    f[1, 11, 39] = np.nan
+    f[2, 11, 39] = np.nan
+    f[30, 6, 20] = np.nan
+    d = O.diagnostics(g, f)
+    assert d[6] == len(bad_nodes)
+    R, _ = W.node_coords(P.nr, P.nth, P.r1, P.r2)
+    w = np.where((np.arange(P.nr) == 0) | (np.arange(P.nr) == P.nr - 1), 0.5, 1.0)
+    dA = (R * w[:, None]) * P.dr * P.dth
+    keep = np.ones((P.nr, P.nth), bool)
+    for i, j in bad_nodes:
+        keep[i, j] = False
+    assert abs(d[0] - 1.3 * dA[keep].sum()) < 1e-12 * d[0]
+    assert np.isfinite(d[:6]).all()
+
+
+@pytest.mark.parametrize("kinds,expect", [((W.WALL, W.WALL), (3, 2)),
+                                          ((W.INFLOW, W.EXTRAPOLATE), (0, 2))])
+def test_step_counts_nonpositive_ghost_states(kinds, expect):
+    """Density falling steeply towards a wall extrapolates to a negative
+    ghost density (ghost0 = 2 rho_0 - rho_1): built at 3 columns by the inner
+    wall and 2 by the outer one, one step reports one bad ghost column each
+    (both ghost layers of a column count once).  An inflow side prescribes
+    its ghost state and reports none."""
+    nr, nth = 8, 16
+    P, F = W.uniform(nr, nth, r1=1.0, r2=2.0, rho=1.0, T=1.0, tau=1e-2,
+                     bc=kinds, bc_par=((1.0, 0.0, 0.0, 1.0), (0.0, 0.0, 0.0, 0.0)))
+    rho = F["rho"].copy()
+    for j in (2, 5, 11):                   # inner wall: rho_0 = 0.2, rho_1 = 1.0
+        rho[0, j] = 0.2
+    for j in (0, 9):                       # outer wall: rho_{nr-1} = 0.3, rho_{nr-2} = 1.0
+        rho[nr - 1, j] = 0.3
+    g = grid_of(P)
+    f0 = O.init_feq(g, rho, F["ur"], F["ut"], F["T"])
+    _, bad = O.step(g, f0, 1)
+    assert bad == sum(expect)
+    # the temperature alone going negative counts too
+    T = F["T"].copy()
+    T[nr - 1, 4] = 0.25                    # T_g0 = 2 * 0.25 - 1 < 0 on the outer side
+    f0 = O.init_feq(g, F["rho"], F["ur"], F["ut"], T)
+    _, bad = O.step(g, f0, 1)
+    assert bad == 1
+
+
+def test_combined_step_is_sum_of_separate_terms():
+    """Eq. combined_scheme is additive from f(t): the relaxation-only step,
+    the r-convection-only step and the theta-convection-only step, each taken
+    from the same f(t), add up (as increments) to the combined step."""
+    P, F = W.smooth_random(9, 24, seed=41, amp=0.05, bc=(W.INFLOW, W.WALL),
+                           bc_par=((1.05, 0.02, 0.01, 1.02), (0.1, 0, 0, 0)))
+    f0 = O.init_feq(grid_of(P), **F) * (1 + 1e-2 * W.noise((33, 9, 24), 1.0, 42))
+    full, _ = O.step(grid_of(P, 7), f0, 1)
+    rel_only, _ = O.step(grid_of(P, 1), f0, 1)
+    r_only, _ = O.step(grid_of(P, 2), f0, 1)
+    t_only, _ = O.step(grid_of(P, 4), f0, 1)
+    summed = rel_only + (r_only - f0) + (t_only - f0)
+    np.testing.assert_allclose(summed, full, rtol=0, atol=4e-16 * np.abs(f0).max())
+    # each part does something on this state
+    for part in (rel_only - f0, r_only - f0, t_only - f0):
+        assert np.abs(part).max() > 1e-6 * np.abs(f0).max()
