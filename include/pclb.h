@@ -61,17 +61,20 @@ enum {
 };
 
 /* Kernel selection for pclb_step / pclb_step_into.  Both kernels give the
- * same result bit for bit.  The strip kernel runs FP32 states with
- * n_theta >= 64 and 9 * 4 * n_r * n_theta < 2^31 bytes; elsewhere the node
- * kernel runs whatever is asked.  Its launch shape can be overridden, for
- * tuning only, with the environment variables PCLB_STRIP_CHUNK (rows per
- * workgroup, 1 to 64), PCLB_STRIP_SPLIT (1, 2 or 4 wavefronts per strip) and
- * PCLB_STRIP_ORDER (1 XCD-contiguous workgroup order, 0 plain), read by
- * pclb_create, which returns PCLB_EINVAL for values out of range. */
+ * same result bit for bit.  The strip kernel runs states with n_theta >= 64
+ * whose planes it can address with 32-bit offsets (checked at creation);
+ * elsewhere the node kernel runs whatever is asked. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
-  PCLB_KERNEL_STRIP = 2    /* r-marching 64-column theta strips with a register ring */
+  PCLB_KERNEL_STRIP = 2    /* r-marching theta strips with a register ring */
+};
+
+/* Workgroup order of the strip kernel (pclb_config.strip_order). */
+enum {
+  PCLB_ORDER_DEFAULT = 0,
+  PCLB_ORDER_XCD = 1,      /* each accelerator die runs a contiguous range of strips */
+  PCLB_ORDER_PLAIN = 2     /* workgroup index order */
 };
 
 typedef struct pclb_config {
@@ -82,9 +85,24 @@ typedef struct pclb_config {
   double dt;             /* time step, > 0 */
   int32_t n_i;           /* directions per speed group; must be 8 (octagon) */
   int32_t n_f;           /* sector count N_f of Sec. II.C; must be 8 (full annulus) */
-  int32_t precision;     /* 32: float storage and convection, double collision;
-                            64: double throughout */
+  int32_t precision;     /* 32: float storage and convection; 64: double throughout */
+  int32_t fp64_collision;/* 1: moments, equilibrium and relaxation in double for
+                            either precision.  The only accepted value: float
+                            collision of a float state drifts from the double
+                            trajectory by 1e-4 relative within 100 steps (the
+                            speed-2.92 and speed-2.99 weights nearly cancel) and
+                            saves no time on this GPU, whose double vector rate
+                            equals its non-packed float rate */
   int32_t kernel;        /* PCLB_KERNEL_* */
+  /* Launch shape of the strip kernel; 0 selects the default.  None of these
+   * changes any result. */
+  int32_t strip_chunk;   /* rows marched by one workgroup, 1..64 */
+  int32_t strip_split;   /* wavefronts sharing one strip: 1, 2 or 4 */
+  int32_t strip_order;   /* PCLB_ORDER_* */
+  double adjoint_tie;    /* relative size below which an upwind difference
+                            counts as zero in pclb_adjoint_step; 0 selects the
+                            default of the precision (1e-13 for 64, 1e-5 for
+                            32); must be >= 0 and < 1e-2 */
 } pclb_config;
 
 /* Courant-number time step: dt = cfl * min(dr, r1*dtheta) / 4.49, 4.49 being
@@ -94,8 +112,9 @@ double pclb_cfl_dt(const pclb_config* cfg, double cfl);
 
 /* Validate cfg and create a context on the current HIP device.  Checks
  * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i = n_f = 8,
- * precision in {32, 64}, and max |C_r|, |C_theta| <= 1 (the monotone range of
- * Sec. II.B, Eqs. varphi_0-varphi2e) -> PCLB_ECFL otherwise.  Allocates the
+ * precision in {32, 64}, fp64_collision = 1, the launch-shape fields and
+ * adjoint_tie in range (PCLB_EINVAL), and max |C_r|, |C_theta| <= 1 (the
+ * monotone range of Sec. II.B, Eqs. varphi_0-varphi2e) -> PCLB_ECFL.  Allocates the
  * context's small device tables and scratch (ghost layers, reduction
  * partials).  *out is owned by the caller until pclb_destroy.  Both radial
  * boundaries start as WALL with omega = 0. */
@@ -162,10 +181,12 @@ int pclb_moments_host(pclb_ctx* ctx, double* diag8_host);
 /* One step of the discrete adjoint of Eq. combined_scheme (not in the paper):
  * lam_out = (d Phi / d f at f_t)^T lam_next, where Phi is the step of
  * pclb_step including the dependence of the radial ghost layers on the two
- * real rows next to each wall.  The MWB switch is differentiated piecewise
- * with sgn(0) = 0 and, where both upwind differences vanish, derivatives
- * (1, 0) of (delta - delta')|delta|/(|delta|+|delta'|) with respect to
- * (delta, delta').  All three buffers hold the context's element type and do
+ * real rows next to each wall.  The MWB switch is differentiated piecewise:
+ * an upwind difference within adjoint_tie times the stencil's magnitude
+ * (|f| summed over its three nodes) counts as zero, sgn(0) = 0, and where
+ * both upwind differences vanish the derivatives of
+ * (delta - delta')|delta|/(|delta|+|delta'|) with respect to (delta, delta')
+ * are (1, 0).  All three buffers hold the context's element type and do
  * not overlap.  Asynchronous. */
 int pclb_adjoint_step(pclb_ctx* ctx, const void* f_t, const void* lam_next, void* lam_out);
 

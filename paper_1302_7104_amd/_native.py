@@ -19,6 +19,7 @@ ERRORS = {
 }
 WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
 KERNEL_AUTO, KERNEL_NODE, KERNEL_STRIP = 0, 1, 2
+ORDER_DEFAULT, ORDER_XCD, ORDER_PLAIN = 0, 1, 2
 
 #: every symbol include/pclb.h declares
 SYMBOLS = (
@@ -40,7 +41,10 @@ class Config(ctypes.Structure):
                 ("r1", ctypes.c_double), ("r2", ctypes.c_double),
                 ("tau", ctypes.c_double), ("dt", ctypes.c_double),
                 ("n_i", ctypes.c_int32), ("n_f", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("fp64_collision", ctypes.c_int32),
+                ("kernel", ctypes.c_int32),
+                ("strip_chunk", ctypes.c_int32), ("strip_split", ctypes.c_int32),
+                ("strip_order", ctypes.c_int32), ("adjoint_tie", ctypes.c_double)]
 
 
 _lib = None

@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -24,16 +25,18 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    objs = []
-    for s in srcs:
-        o = os.path.join(CSRC, os.path.basename(s) + ".o")
-        lang = ["-x", "hip"]
-        cmd = [HIPCC, *FLAGS, *lang, "-c", s, "-o", o]
-        cmd = [c for c in cmd if c != "-shared"]
+    objs = [os.path.join(CSRC, os.path.basename(s) + ".o") for s in srcs]
+
+    def compile_one(so):
+        s, o = so
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-x", "hip", "-c", s, "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(o)
+
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 1)) as ex:
+        list(ex.map(compile_one, zip(srcs, objs)))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -119,12 +119,6 @@ __device__ inline MwbD mwb_grad(double aC, double K, double c, double u1, double
   return mwb_grad_t<double>(aC, K, c, u1, u2, eps);
 }
 
-// Tie threshold per storage precision: a few hundred ulps of the stored values
-// (rounding differences of f^eq scale with sum |f| / rho, up to about 16 here).
-template <class R> struct TieEps;
-template <> struct TieEps<double> { static constexpr double value = 1e-13; };
-template <> struct TieEps<float> { static constexpr double value = 1e-5; };
-
 template <class R>
 __device__ inline double fetch_f(const R* __restrict__ f, const R* __restrict__ ghost, int q, int i,
                                  int j, int nr, int nth, size_t plane) {

@@ -26,7 +26,7 @@ template <class R>
 __global__ void __launch_bounds__(128) ghost_adjoint_kernel(Tables T, BCdev bc, const R* __restrict__ f,
                                                             const R* __restrict__ lam,
                                                             const R* __restrict__ ghost,
-                                                            double* __restrict__ gm) {
+                                                            double tie, double* __restrict__ gm) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int side = blockIdx.y;
   if (j >= T.nth) return;
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(128) ghost_adjoint_kernel(Tables T, BCdev bc, 
   const int gsgn = side == 0 ? -1 : 1;     // direction from the wall row into the ghosts
   const double ct = T.cth[j], st = T.sth[j];
   const int kind = bc.kind[side];
-  constexpr double TE = TieEps<R>::value;
+  const double TE = tie;
   // macroscopic state of the two real rows
   double m0[4], m1[4];
   {
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
                                                            const R* __restrict__ lam,
                                                            const R* __restrict__ ghost,
                                                            const double* __restrict__ gm,
-                                                           R* __restrict__ out) {
+                                                           double tie, R* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= T.nth) return;
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
   const double e = T.e;
   // MWB derivatives in the state's precision
   using A = R;
-  const A TEa = (A)TieEps<R>::value;
+  const A TEa = (A)tie;
   // moment cotangent of this node from the relaxation's f^eq
   double gM[4];
   {
@@ -267,15 +267,15 @@ __global__ void __launch_bounds__(128) adjoint_init_kernel(Tables T, const R* __
 
 template <class R>
 hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const void* lam,
-                          void* lam_out, void* ghost, double* gm, hipStream_t s) {
+                          void* lam_out, void* ghost, double* gm, double tie, hipStream_t s) {
   hipError_t e = launch_ghost<R>(T, bc, f, ghost, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ghost_adjoint_kernel<R>, dim3((T.nth + 127) / 128, 2), dim3(128), 0, s, T, bc,
-                     (const R*)f, (const R*)lam, (const R*)ghost, gm);
+                     (const R*)f, (const R*)lam, (const R*)ghost, tie, gm);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adjoint_node_kernel<R>, dim3((T.nth + 127) / 128, T.nr), dim3(128), 0, s, T,
-                     (const R*)f, (const R*)lam, (const R*)ghost, (const double*)gm, (R*)lam_out);
+                     (const R*)f, (const R*)lam, (const R*)ghost, (const double*)gm, tie, (R*)lam_out);
   return hipGetLastError();
 }
 
@@ -289,9 +289,9 @@ hipError_t launch_adjoint_init(const Tables& T, const void* lam, const double* r
 }
 
 template hipError_t launch_adjoint<float>(const Tables&, const BCdev&, const void*, const void*, void*,
-                                          void*, double*, hipStream_t);
+                                          void*, double*, double, hipStream_t);
 template hipError_t launch_adjoint<double>(const Tables&, const BCdev&, const void*, const void*, void*,
-                                           void*, double*, hipStream_t);
+                                           void*, double*, double, hipStream_t);
 template hipError_t launch_adjoint_init<float>(const Tables&, const void*, const double*, const double*,
                                                const double*, const double*, double*, double*, double*,
                                                double*, hipStream_t);

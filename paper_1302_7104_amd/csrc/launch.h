@@ -40,7 +40,7 @@ int diag_slots();
 // Adjoint.
 template <class R>
 hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const void* lam,
-                          void* lam_out, void* ghost, double* gm, hipStream_t s);
+                          void* lam_out, void* ghost, double* gm, double tie, hipStream_t s);
 template <class R>
 hipError_t launch_adjoint_init(const Tables& T, const void* lam, const double* rho,
                                const double* ur, const double* ut, const double* Tt, double* d_rho,

@@ -4,7 +4,6 @@
 
 #include <cmath>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,6 +26,7 @@ struct pclb_ctx {
   hipStream_t stream = nullptr;
   int64_t steps = 0;
   StripTune tune;               // strip kernel launch shape
+  double tie = 0;               // adjoint tie threshold
   // context-owned device memory
   double* d_geom = nullptr;     // cth[nth], sth[nth], rinv[nr], wA[nr]
   void* d_ghost = nullptr;      // 4 * 33 * nth elements of the state type
@@ -66,7 +66,20 @@ int validate(const pclb_config* c, std::string& why) {
   if (c->n_i != 8) { why = "only the octagon model (n_i = 8) is built"; return PCLB_EINVAL; }
   if (c->n_f != 8) { why = "only the full annulus (n_f = n_i = 8) is built"; return PCLB_EINVAL; }
   if (c->precision != 32 && c->precision != 64) { why = "precision must be 32 or 64"; return PCLB_EINVAL; }
+  if (c->fp64_collision != 1) {
+    why = "fp64_collision must be 1 (float collision is not offered: it loses accuracy and no time)";
+    return PCLB_EINVAL;
+  }
   if (c->kernel < 0 || c->kernel > 2) { why = "unknown kernel selection"; return PCLB_EINVAL; }
+  if (c->strip_chunk < 0 || c->strip_chunk > 64 || c->strip_split < 0 || c->strip_split == 3 ||
+      c->strip_split > 4 || c->strip_order < 0 || c->strip_order > 2) {
+    why = "strip launch shape out of range (strip_chunk 0-64, strip_split 0, 1, 2 or 4, strip_order 0-2)";
+    return PCLB_EINVAL;
+  }
+  if (!(c->adjoint_tie >= 0.0) || !(c->adjoint_tie < 1e-2)) {
+    why = "adjoint_tie must be in [0, 1e-2)";
+    return PCLB_EINVAL;
+  }
   double dr = (c->r2 - c->r1) / (c->n_r - 1);
   double dth = 2.0 * PI / c->n_theta;
   double vmax = speed(NK);
@@ -116,17 +129,11 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   pclb_ctx* c = new (std::nothrow) pclb_ctx();
   if (!c) return fail(nullptr, PCLB_ENOMEM, "host allocation failed");
   c->cfg = *cfg;
-  // tuning knobs of the strip kernel (launch shape only; results do not change)
-  if (const char* v = std::getenv("PCLB_STRIP_CHUNK")) c->tune.chunk = std::atoi(v);
-  if (const char* v = std::getenv("PCLB_STRIP_SPLIT")) c->tune.split = std::atoi(v);
-  if (const char* v = std::getenv("PCLB_STRIP_ORDER")) c->tune.order = std::atoi(v);
-  if (c->tune.chunk < 0 || c->tune.chunk > 64 || c->tune.split < 0 || c->tune.split == 3 ||
-      c->tune.split > 4 || c->tune.order > 1) {
-    delete c;
-    return fail(nullptr, PCLB_EINVAL,
-                "strip launch shape out of range (PCLB_STRIP_CHUNK 1-64, PCLB_STRIP_SPLIT 1, 2 "
-                "or 4, PCLB_STRIP_ORDER 0 or 1)");
-  }
+  // launch shape of the strip kernel (results do not depend on it)
+  c->tune.chunk = cfg->strip_chunk;
+  c->tune.split = cfg->strip_split;
+  c->tune.order = cfg->strip_order == PCLB_ORDER_PLAIN ? 0 : 1;
+  c->tie = cfg->adjoint_tie > 0.0 ? cfg->adjoint_tie : (cfg->precision == 64 ? 1e-13 : 1e-5);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return fail(nullptr, PCLB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
   const int nr = cfg->n_r, nth = cfg->n_theta;
@@ -322,8 +329,8 @@ int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* 
   if (!f_t || !lam_next || !lam_out || lam_out == lam_next || lam_out == f_t)
     return fail(c, PCLB_EINVAL, "three non-null buffers, lam_out distinct from the inputs");
   hipError_t e = c->cfg.precision == 32
-                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->stream)
-                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->stream);
+                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream)
+                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
   return PCLB_OK;
 }

@@ -31,7 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 def cfg(**kw):
     base = dict(n_r=64, n_theta=128, r1=1.0, r2=2.0, tau=1e-4, dt=1e-3, n_i=8, n_f=8,
-                precision=64, kernel=0)
+                precision=64, fp64_collision=1, kernel=0, strip_chunk=0, strip_split=0,
+                strip_order=0, adjoint_tie=0.0)
     base.update(kw)
     return N.Config(*[base[k] for k, _ in N.Config._fields_])
 
@@ -47,6 +48,7 @@ def test_cfl_dt_matches_workload_rule():
     (dict(r1=0.0), -1), (dict(r2=0.5), -1), (dict(n_r=3), -1), (dict(n_theta=4), -1),
     (dict(tau=0.0), -1), (dict(dt=-1.0), -1), (dict(n_i=16), -1), (dict(n_f=1), -1),
     (dict(precision=16), -1), (dict(kernel=7), -1), (dict(dt=0.01), -2),
+    (dict(fp64_collision=0), -1), (dict(adjoint_tie=-1.0), -1), (dict(adjoint_tie=0.5), -1),
 ])
 def test_create_rejects_invalid_config(kw, code):
     L = N.lib()
@@ -57,16 +59,16 @@ def test_create_rejects_invalid_config(kw, code):
     assert L.pclb_last_error(None)
 
 
-@pytest.mark.parametrize("var,val", [("PCLB_STRIP_CHUNK", "65"), ("PCLB_STRIP_CHUNK", "-1"),
-                                     ("PCLB_STRIP_SPLIT", "3"), ("PCLB_STRIP_ORDER", "2")])
-def test_create_rejects_strip_shape_out_of_range(var, val, monkeypatch):
+@pytest.mark.parametrize("field,val", [("strip_chunk", 65), ("strip_chunk", -1),
+                                       ("strip_split", 3), ("strip_split", 8),
+                                       ("strip_order", 3)])
+def test_create_rejects_strip_shape_out_of_range(field, val):
     """The strip kernel holds 1/r of a chunk one row per lane: more than 64
     rows per chunk (or an unknown split or order) is refused at creation,
     before any device call."""
-    monkeypatch.setenv(var, val)
     L = N.lib()
     ctx = ctypes.c_void_p()
-    rc = L.pclb_create(ctypes.byref(cfg()), ctypes.byref(ctx))
+    rc = L.pclb_create(ctypes.byref(cfg(**{field: val})), ctypes.byref(ctx))
     assert rc == -1
     assert not ctx.value
     assert b"launch shape" in L.pclb_last_error(None)

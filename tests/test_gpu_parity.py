@@ -28,9 +28,9 @@ def _gpu():
     _native.lib()          # raises if the library is missing: no fallback
 
 
-def sim_of(P, precision, kernel=0):
+def sim_of(P, precision, kernel=0, **kw):
     from paper_1302_7104_amd.sim import Sim
-    return Sim(P, precision=precision, kernel=kernel)
+    return Sim(P, precision=precision, kernel=kernel, **kw)
 
 
 def grid_of(P):
@@ -248,7 +248,7 @@ def test_node_and_strip_kernels_bitwise_equal():
 
 
 @pytest.mark.parametrize("shape", [(33, 66), (12, 64), (9, 129), (20, 4000), (40, 250)])
-def test_strip_launch_shapes_bitwise_equal_node_kernel(shape, monkeypatch):
+def test_strip_launch_shapes_bitwise_equal_node_kernel(shape):
     """The FP32 strip kernel in every launch shape (wavefronts per strip,
     rows per chunk, workgroup order) equals the node kernel bit for bit:
     ragged last strips, odd N_theta (halo pairs not adjacent), a single strip,
@@ -262,12 +262,9 @@ def test_strip_launch_shapes_bitwise_equal_node_kernel(shape, monkeypatch):
     s.step(6)
     want = s.state.cpu().numpy()
     s.close()
-    for split, chunk, order in [(1, 0, 1), (2, 0, 1), (4, 0, 1), (2, 7, 0), (2, 1, 1), (4, 3, 0),
-                                (2, 64, 1), (2, 5, 1), (2, 6, 0)]:
-        monkeypatch.setenv("PCLB_STRIP_SPLIT", str(split))
-        monkeypatch.setenv("PCLB_STRIP_CHUNK", str(chunk))
-        monkeypatch.setenv("PCLB_STRIP_ORDER", str(order))
-        s = sim_of(P, 32, N.KERNEL_STRIP)
+    for split, chunk, order in [(1, 0, 1), (2, 0, 1), (4, 0, 1), (2, 7, 2), (2, 1, 1), (4, 3, 2),
+                                (2, 64, 1), (2, 5, 1), (2, 6, 2)]:
+        s = sim_of(P, 32, N.KERNEL_STRIP, strip_split=split, strip_chunk=chunk, strip_order=order)
         s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
         s.step(6)
         got = s.state.cpu().numpy()
@@ -317,21 +314,42 @@ def test_fields_match_oracle():
 # --------------------------------------------------------------------------
 # Adjoint
 
+def local_scale(w, lam):
+    """Per-entry scale of an adjoint comparison: |w| plus the largest |lam|
+    over all velocities in the entry's 5 x 5 neighbourhood (theta periodic),
+    the size of the terms that meet in the entry."""
+    m = np.abs(lam).max(0)
+    out = np.zeros_like(m)
+    nr = m.shape[0]
+    for di in range(-2, 3):
+        rows = np.clip(np.arange(nr) + di, 0, nr - 1)
+        for dj in range(-2, 3):
+            out = np.maximum(out, np.roll(m[rows], -dj, axis=1))
+    return np.abs(w) + out[None]
+
+
 @pytest.mark.parametrize("bc", BCS)
 def test_adjoint_step_parity(bc):
     """One adjoint step on a noisy smooth state, both sides given the same
-    state (the oracle's, rounded to the run's precision on the host).
+    state (the oracle's, rounded to the run's precision on the host) and the
+    same tie threshold of the switch's derivative.
 
-    The MWB switch is not differentiable where an upwind difference vanishes;
-    both sides count a difference within a tie threshold (1e-13 FP64, 1e-5
-    FP32, relative to the stencil) as zero.  Entries whose oracle value moves
-    when that threshold moves by 1% sit at such a branch point: there either
-    branch is a valid one-sided derivative, and the GPU value must equal one
-    of the two.  All other entries are compared as a whole."""
+    Each entry is bounded on its own, relative to its local scale (its size
+    plus the largest cotangent in its neighbourhood).  Entries whose oracle
+    value moves when the tie threshold moves by 1% sit at a branch point of
+    the switch: there the GPU value must equal one of the two oracle values,
+    to the same per-entry bound.  In FP32 the two rows next to each wall are
+    held to a bound of their own: their stencils contain the ghost layers,
+    which the FP32 path (as its forward step) rounds to float and the oracle
+    keeps in double."""
     P, F = smooth_problem(21, 70, bc, 12)
     g = grid_of(P)
-    for prec, tol in ((64, 1e-12), (32, 1e-5), (64, 1e-12), (32, 1e-5)):
+    wall = np.zeros((P.nr, P.nth), bool)
+    wall[:2] = wall[-2:] = True
+    for prec, tie, tol, tol_wall in ((64, 1e-13, 1e-12, 1e-12), (32, 1e-5, 2e-6, 1e-3)):
         s, f_or = start(P, F, prec, noise_seed=13, amp=1e-2)
+        s.close()
+        s = sim_of(P, prec, adjoint_tie=tie)
         f_in = f_or.astype(np.float32).astype(np.float64) if prec == 32 else f_or
         s.load_state(torch.as_tensor(f_in, dtype=s.dtype, device=s.device))
         lam = W.noise((33, P.nr, P.nth), 1.0, 14)
@@ -341,22 +359,18 @@ def test_adjoint_step_parity(bc):
         s.adjoint_step(s.state, lam_t, out)
         got = out.double().cpu().numpy()
         assert np.isfinite(got).all()
-        tie = 1e-5 if prec == 32 else 1e-13
-        want = {}
-        try:
-            for t in (tie, 0.99 * tie, 1.01 * tie):
-                O.set_tie(t)
-                want[t] = O.adjoint_step(g, f_in, lam_in)
-        finally:
-            O.set_tie(1e-13)
-        w0, wlo, whi = want[tie], want[0.99 * tie], want[1.01 * tie]
-        scale = np.abs(w0).max()
-        branch = np.abs(wlo - whi) > 1e-9 * scale
+        w0 = O.adjoint_step(g, f_in, lam_in, tie_eps=tie)
+        wlo = O.adjoint_step(g, f_in, lam_in, tie_eps=0.99 * tie)
+        whi = O.adjoint_step(g, f_in, lam_in, tie_eps=1.01 * tie)
+        sc = local_scale(w0, lam_in)
+        branch = (np.abs(wlo - whi) > 1e-9 * sc) | (np.abs(wlo - w0) > 1e-9 * sc)
+        err = np.abs(got - w0) / sc
+        err = np.where(branch, np.minimum(np.abs(got - wlo), np.abs(got - whi)) / sc, err)
+        bound = np.where(wall[None], tol_wall, tol)
+        print(f"precision {prec}: branch entries {int(branch.sum())}, max error / local scale: "
+              f"interior {err[:, ~wall].max():.3e}, wall rows {err[:, wall].max():.3e}")
         assert branch.sum() <= 1e-3 * branch.size, branch.sum()
-        unique = ~branch
-        assert rel(got[unique], w0[unique]) <= tol, (prec, rel(got[unique], w0[unique]))
-        near = np.minimum(np.abs(got - wlo), np.abs(got - whi))[branch]
-        assert (near <= 1e3 * tol * scale).all(), (prec, near.max() / scale)
+        assert (err <= bound).all(), (prec, err[:, ~wall].max(), err[:, wall].max())
 
 
 def test_adjoint_init_parity():
