@@ -3,15 +3,18 @@
 
 Workload (the headline configuration): Kelvin-Helmholtz shear layer on the
 annulus r in [0.5, 1.5] with 4096 x 8192 nodes and 33 velocities, FP32 state,
-CFL 0.3, tau = 1e-5; W warm-up steps, then K timed steps.  One step = one
-pass of the whole hot path (radial ghost layers, moments, equilibrium,
-relaxation, MWB convection in r and theta, store) over the whole grid.
+tau = 1e-5, Courant number 0.25 (the recipe's: the combined scheme is
+unstable next to the inner wall at 0.3); W warm-up steps, then K timed steps.
+One step = one pass of the whole hot path (radial ghost layers, moments,
+equilibrium, relaxation, MWB convection in r and theta, store) over the whole
+grid.  The time per step does not depend on the Courant number.
 
 Printed: one JSON line with the metric (G cell-velocity updates per second),
 the roofline of the step kernel (algorithmic bytes / kernel time vs 8 TB/s),
 the CPU oracle timed on this host on a bounded sample, and extra figures: the
-FP64 step on the same grid and the adjoint/forward cost ratio on the
-1024 x 2048 Richtmyer-Meshkov adjoint configuration.
+FP64 step on the same grid, the adjoint/forward cost ratio on the
+1024 x 2048 Richtmyer-Meshkov adjoint configuration, and the FP32 error
+against FP64 after the full run of every configuration.
 """
 from __future__ import annotations
 
@@ -196,26 +199,127 @@ def adjoint_kernel_times(W, torch, steps=50):
     return res
 
 
-def cpu_baseline(W, target_s=25.0):
+#: the configurations run to their full length for the FP32 error statement:
+#: name -> (recipe, n_r, n_theta, steps)
+ACCURACY_RUNS = {
+    "rotation_64x128": ("rotation", 64, 128, 200),
+    "shock_tube_512x1024": ("shock_tube", 512, 1024, 2000),
+    "richtmyer_meshkov_2048x4096": ("richtmyer_meshkov", 2048, 4096, 5000),
+    "kelvin_helmholtz_4096x8192": ("kelvin_helmholtz", 4096, 8192, 1050),
+    "adjoint_rm_1024x2048": ("richtmyer_meshkov", 1024, 2048, 200),
+}
+
+
+def smooth_mask(torch, rho, jump=0.01, width=2):
+    """Nodes whose (2 width + 1)^2 neighbourhood (theta periodic, r clamped)
+    holds no relative density jump above `jump`: (max - min) / rho < jump."""
+    hi = rho.clone()
+    lo = rho.clone()
+    nr = rho.shape[0]
+    for di in range(-width, width + 1):
+        rows = torch.clamp(torch.arange(nr, device=rho.device) + di, 0, nr - 1)
+        shifted = rho[rows]
+        for dj in range(-width, width + 1):
+            x = torch.roll(shifted, -dj, dims=1)
+            hi = torch.maximum(hi, x)
+            lo = torch.minimum(lo, x)
+    return (hi - lo) / rho < jump
+
+
+def moment_errors(torch, fa, fb, mask):
+    """Largest relative errors of field set fa against the reference fb over
+    the masked nodes: rho and T relative, the velocity relative to the local
+    sound speed sqrt(2 T) (gamma = 2)."""
+    rho, T = fb["rho"], fb["T"]
+    c = torch.sqrt(2.0 * T)
+    du = torch.sqrt((fa["ur"] - fb["ur"]) ** 2 + (fa["ut"] - fb["ut"]) ** 2) / c
+    out = {}
+    for key, err in (("rho", (fa["rho"] - rho).abs() / rho), ("T", (fa["T"] - T).abs() / T),
+                     ("u_over_c", du)):
+        out[key] = float(err[mask].max().item()) if bool(mask.any()) else 0.0
+        out[key + "_all_nodes"] = float(err.max().item())
+    return out
+
+
+def fp32_accuracy(W, torch, name):
+    """FP32 against FP64 after the full run of one configuration: both
+    precisions through the HIP path from the same fields (the FP64 path is
+    the one the parity tests hold to the oracle).  Returns the smooth-region
+    errors of rho, T and u, the share of nodes in the smooth region, the
+    largest errors over all nodes, and the same errors for an FP64 run started
+    from the initial state rounded to float (how much the flow itself
+    amplifies a perturbation of the size of float rounding)."""
+    from paper_1302_7104_amd.sim import Sim
+    recipe, nr, nth, steps = ACCURACY_RUNS[name]
+    P, F = getattr(W, recipe)(nr=nr, nth=nth, steps=steps)
+    fields = {}
+    for key, prec in (("fp64", 64), ("fp32", 32), ("fp64_rounded_start", 64)):
+        sim = Sim(P, precision=prec)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        if key == "fp64_rounded_start":
+            sim.state.copy_(sim.state.float().double())
+        sim.step(steps)
+        fields["diag_" + key] = sim.diagnostics_host()
+        fields[key] = sim.fields()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    mask = smooth_mask(torch, fields["fp64"]["rho"])
+    res = moment_errors(torch, fields["fp32"], fields["fp64"], mask)
+    res["steps"] = steps
+    res["cfl"] = W.CFL[recipe]
+    res["smooth_fraction"] = float(mask.double().mean().item())
+    d32, d64 = fields["diag_fp32"], fields["diag_fp64"]
+    res["mass_rel_fp32_vs_fp64"] = abs(d32[0] - d64[0]) / d64[0]
+    res["fp64_rounded_start"] = moment_errors(torch, fields["fp64_rounded_start"], fields["fp64"], mask)
+    del fields
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, target_s=20.0, one_thread_s=5.0):
     """The FP64 CPU oracle, as it stands, on the same recipe at 512 x 1024
-    (cost per cell-velocity update does not depend on the grid size)."""
+    (cost per cell-velocity update does not depend on the grid size), on all
+    the host threads OpenMP offers and on one thread."""
     from oracle import oracle as O
     O.build(force=False)
     P, F = W.kelvin_helmholtz(512, 1024, 1)
-    g = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par)
+    g = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par, nf=P.nf)
     f = O.init_feq(g, **F)
-    f, _ = O.step(g, f, 1)                       # thread pool start-up
-    t0 = time.perf_counter()
-    f, _ = O.step(g, f, 2)
-    one = (time.perf_counter() - t0) / 2
-    n = max(1, int(target_s / max(one, 1e-3)))
-    t0 = time.perf_counter()
-    f, _ = O.step(g, f, n)
-    dt = time.perf_counter() - t0
-    rate = NQ * P.nr * P.nth * n / dt / 1e9
-    return {"value": rate, "unit": "Gcell\u00b7vel/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"kelvin_helmholtz recipe at 512x1024 (33 velocities), {n} FP64 steps, "
-                      f"{dt:.1f} s on {O.num_threads()} OpenMP threads"}
+
+    def rate(budget):
+        nonlocal f
+        f, _ = O.step(g, f, 1)                   # thread pool start-up
+        t0 = time.perf_counter()
+        f, _ = O.step(g, f, 1)
+        one = time.perf_counter() - t0
+        n = max(1, int(budget / max(one, 1e-3)))
+        t0 = time.perf_counter()
+        f, _ = O.step(g, f, n)
+        dt = time.perf_counter() - t0
+        return NQ * P.nr * P.nth * n / dt / 1e9, n, dt
+
+    threads = O.num_threads()
+    r_all, n_all, t_all = rate(target_s)
+    O.set_threads(1)
+    r_one, n_one, t_one = rate(one_thread_s)
+    O.set_threads(threads)
+    return {"value": r_all, "unit": "Gcell\u00b7vel/s", "cores": threads, "kind": "oracle",
+            "one_thread_value": r_one, "cpu": cpu_model(),
+            "sample": f"kelvin_helmholtz recipe at 512x1024 (33 velocities): {n_all} FP64 steps "
+                      f"in {t_all:.1f} s on {threads} OpenMP threads, {n_one} steps in "
+                      f"{t_one:.1f} s on one thread"}
 
 
 def calibrate_copy(torch, gib=1):
@@ -292,6 +396,8 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time the adjoint step alone against the forward step (1024 x 2048 "
                          "Richtmyer-Meshkov) and exit")
+    ap.add_argument("--accuracy-only", action="store_true",
+                    help="FP32 error against FP64 after the full run of every configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -325,6 +431,10 @@ def main():
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_rm_1024x2048": adjoint_kernel_times(W, torch)}), flush=True)
+        return
+    if args.accuracy_only:
+        for name in ACCURACY_RUNS:
+            print(json.dumps({name: fp32_accuracy(W, torch, name)}), flush=True)
         return
     P, ms, diag = run_forward(W, Sim, torch, 32, args.steps, args.warmup)
     if args.calibrate_copy:
@@ -361,6 +471,8 @@ def main():
         extra["fp64_gcellvel_per_s"] = cellvel / (ms64 * 1e-3) / 1e9
         extra["fp64_hbm_frac"] = (2 * NQ * nodes * 8) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS
         extra["adjoint_rm_1024x2048"] = run_adjoint(W, torch)
+        extra["fp32_error_vs_fp64_after_run"] = {name: fp32_accuracy(W, torch, name)
+                                                 for name in ACCURACY_RUNS}
     out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)

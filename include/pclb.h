@@ -61,13 +61,17 @@ enum {
 };
 
 /* Kernel selection for pclb_step / pclb_step_into.  Both kernels give the
- * same result bit for bit.  The strip kernel runs states with n_theta >= 64
- * whose planes it can address with 32-bit offsets (checked at creation);
- * elsewhere the node kernel runs whatever is asked. */
+ * same result bit for bit.  The strip kernel runs float states of the full
+ * annulus (n_f = 8) with n_theta >= 64 whose planes it can address with
+ * 32-bit offsets; its strips of 64 columns that straddle an octant boundary
+ * theta = m pi/4 (none when n_theta is a multiple of 512) run in a second
+ * launch of a variant that selects upwind sides per lane.  Everything else
+ * (double states, sectors, narrow grids) runs on the node kernel, whatever
+ * is asked. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
-  PCLB_KERNEL_STRIP = 2    /* r-marching theta strips with a register ring */
+  PCLB_KERNEL_STRIP = 2    /* r-marching 64-column theta strips with a register ring */
 };
 
 /* Workgroup order of the strip kernel (pclb_config.strip_order). */
@@ -84,7 +88,10 @@ typedef struct pclb_config {
   double tau;            /* relaxation time (Eq. FDLBM), > 0 */
   double dt;             /* time step, > 0 */
   int32_t n_i;           /* directions per speed group; must be 8 (octagon) */
-  int32_t n_f;           /* sector count N_f of Sec. II.C; must be 8 (full annulus) */
+  int32_t n_f;           /* N_f of Sec. II.C, 1..8: theta covers 0 < theta <= 2 pi n_f / 8,
+                            dtheta = 2 pi n_f / (8 n_theta), and for n_f < 8 the
+                            azimuthal ghosts rotate the direction index by n_f
+                            (Fig. 3); 8 is the full annulus */
   int32_t precision;     /* 32: float storage and convection; 64: double throughout */
   int32_t fp64_collision;/* 1: moments, equilibrium and relaxation in double for
                             either precision.  The only accepted value: float
@@ -97,11 +104,10 @@ typedef struct pclb_config {
   /* Launch shape of the strip kernel; 0 selects the default.  None of these
    * changes any result. */
   int32_t strip_chunk;   /* rows marched by one workgroup, 1..64 */
-  int32_t strip_split;   /* wavefronts sharing one strip: 1, 2 or 4 */
   int32_t strip_order;   /* PCLB_ORDER_* */
   double adjoint_tie;    /* relative size below which an upwind difference
                             counts as zero in pclb_adjoint_step; 0 selects the
-                            default of the precision (1e-13 for 64, 1e-5 for
+                            default of the precision (1e-13 for 64, 1e-6 for
                             32); must be >= 0 and < 1e-2 */
 } pclb_config;
 
@@ -111,7 +117,7 @@ typedef struct pclb_config {
 double pclb_cfl_dt(const pclb_config* cfg, double cfl);
 
 /* Validate cfg and create a context on the current HIP device.  Checks
- * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i = n_f = 8,
+ * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i = 8, n_f in 1..8,
  * precision in {32, 64}, fp64_collision = 1, the launch-shape fields and
  * adjoint_tie in range (PCLB_EINVAL), and max |C_r|, |C_theta| <= 1 (the
  * monotone range of Sec. II.B, Eqs. varphi_0-varphi2e) -> PCLB_ECFL.  Allocates the
@@ -177,6 +183,29 @@ int pclb_moments_of(pclb_ctx* ctx, const void* f, double* rho, double* u_r, doub
 /* Synchronizing variant: diagnostics of the current state copied to the host
  * array diag8_host.  Returns PCLB_ENONFINITE if any node is non-finite. */
 int pclb_moments_host(pclb_ctx* ctx, double* diag8_host);
+
+/* Non-equilibrium fields of Sec. IV (Eqs. M_relative, M_absolute, D_relative,
+ * D_absolute), the mask bits of pclb_noneq. */
+enum {
+  PCLB_NONEQ_M = 1,       /* moments M_m = sum f v...v */
+  PCLB_NONEQ_MSTAR = 2,   /* central moments M*_m = sum f (v-u)...(v-u) */
+  PCLB_NONEQ_DELTA = 4,   /* Delta_m = M_m(f - f^eq) */
+  PCLB_NONEQ_DSTAR = 8,   /* Delta*_m = M*_m(f - f^eq) */
+  PCLB_NONEQ_ALL = 15
+};
+
+/* The non-equilibrium fields of f (the current state if f is NULL) for
+ * m in {2, 3, (3,1), (4,2)} with M_{3,1} = sum (1/2) f |v|^2 v and
+ * M_{4,2} = sum (1/2) f |v|^2 v v, u the node's flow velocity and f^eq the
+ * discrete equilibrium of the node's rho, u, E (summed from the 33 values,
+ * not from closed forms).  out is a device array of doubles
+ * [n_kinds][12][n_r][n_theta]: the kinds selected by `kinds` in the order
+ * M, M*, Delta, Delta*, and per kind the 12 components in the node's polar
+ * basis (e_r, e_theta): M_2 rr, r theta, theta theta; M_3 rrr, rr theta,
+ * r theta theta, theta theta theta; M_{3,1} r, theta; M_{4,2} rr, r theta,
+ * theta theta.  Computed in double.  Asynchronous.  PCLB_EINVAL for an empty
+ * or unknown mask or a null out. */
+int pclb_noneq(pclb_ctx* ctx, const void* f, int32_t kinds, double* out);
 
 /* One step of the discrete adjoint of Eq. combined_scheme (not in the paper):
  * lam_out = (d Phi / d f at f_t)^T lam_next, where Phi is the step of

@@ -44,7 +44,7 @@ class _OrGrid(ctypes.Structure):
                 ("tau", ctypes.c_double), ("dt", ctypes.c_double),
                 ("bc_kind", ctypes.c_int32 * 2),
                 ("bc_par", (ctypes.c_double * 4) * 2),
-                ("terms", ctypes.c_int32)]
+                ("terms", ctypes.c_int32), ("nf", ctypes.c_int32)]
 
 
 @dataclass
@@ -60,8 +60,11 @@ class Grid:
     bc_kind: tuple = (WALL, WALL)
     bc_par: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
     terms: int = 7
+    nf: int = 8           # theta covers 2 pi nf / 8 (Sec. II.C); 8 = full annulus
 
     def c(self) -> _OrGrid:
+        if not 1 <= int(self.nf) <= 8:
+            raise ValueError("nf must be in 1..8")
         g = _OrGrid()
         g.nr, g.nth = self.nr, self.nth
         g.r1, g.r2, g.tau, g.dt = self.r1, self.r2, self.tau, self.dt
@@ -71,6 +74,7 @@ class Grid:
             for a in range(4):
                 g.bc_par[s][a] = float(p[a])
         g.terms = self.terms
+        g.nf = int(self.nf)
         return g
 
 
@@ -103,6 +107,8 @@ def lib():
         L.or_diagnostics.argtypes = [G, _D, _D]
         L.or_adjoint_step.argtypes = [G, _D, _D, ctypes.c_double, _D]
         L.or_adjoint_init.argtypes = [G, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.or_noneq.argtypes = [G, _D, _D]
+        L.or_noneq_sample.argtypes = [G, _D, _I, ctypes.c_int32, _D]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_threads.argtypes = [ctypes.c_int32]
         _lib = L
@@ -245,6 +251,31 @@ def adjoint_init(grid: Grid, rho, ur, ut, T, lam):
     lib().or_adjoint_init(ctypes.byref(g), _p(rho), _p(ur), _p(ut), _p(T), _p(lam),
                           *(_p(o) for o in outs))
     return tuple(outs)
+
+
+#: names of the 12 polar components of each non-equilibrium kind
+NONEQ_COMPONENTS = ("M2_rr", "M2_rt", "M2_tt", "M3_rrr", "M3_rrt", "M3_rtt", "M3_ttt",
+                    "M31_r", "M31_t", "M42_rr", "M42_rt", "M42_tt")
+
+
+def noneq(grid: Grid, f: np.ndarray) -> np.ndarray:
+    """Sec. IV: (4, 12, nr, nth) array of M_m, M*_m, Delta_m, Delta*_m for
+    m in {2, 3, (3,1), (4,2)}, polar components (NONEQ_COMPONENTS)."""
+    f = _f64(f)
+    out = np.empty((4, 12, grid.nr, grid.nth))
+    g = grid.c()
+    lib().or_noneq(ctypes.byref(g), _p(f), _p(out))
+    return out
+
+
+def noneq_sample(grid: Grid, f: np.ndarray, nodes) -> np.ndarray:
+    """``noneq`` at the listed (i, j) nodes only: (len(nodes), 4, 12)."""
+    f = _f64(f)
+    nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.int32).reshape(-1, 2))
+    out = np.empty((len(nd), 4, 12))
+    g = grid.c()
+    lib().or_noneq_sample(ctypes.byref(g), _p(f), nd.ctypes.data_as(_I), len(nd), _p(out))
+    return out
 
 
 def num_threads() -> int:

@@ -288,6 +288,7 @@ struct OrGrid {
   int32_t bc_kind[2];
   double bc_par[2][4];
   int32_t terms;
+  int32_t nf;   // N_f: theta covers 0 < theta <= 2 pi N_f / N_i (N_i = 8; 8 = full annulus)
 };
 
 namespace {
@@ -298,7 +299,7 @@ struct Geometry {
   std::vector<double> r, ct, st;
   explicit Geometry(const OrGrid& g) : nr(g.nr), nth(g.nth) {
     dr = (g.r2 - g.r1) / (nr - 1);
-    dth = 2.0 * PI / nth;
+    dth = 2.0 * PI * g.nf / (NI * (double)nth);     // Sec. II.C: 2 pi N_f / (N_i N_theta)
     r.resize(nr + 4);                      // r of rows -2..nr+1
     for (int i = -2; i < nr + 2; ++i) r[i + 2] = g.r1 + i * dr;
     ct.resize(nth); st.resize(nth);
@@ -322,6 +323,31 @@ struct Padded {
 
 inline size_t idx(const OrGrid& g, int q, int i, int j) {
   return ((size_t)q * g.nr + i) * g.nth + j;
+}
+
+// mod{a, b} of Sec. II.B: a for a <= b, a - b above (a in 1..2b).
+inline int paper_mod(int a, int b) { return a <= b ? a : a - b; }
+
+// Sec. II.C, azimuthal boundary condition (Fig. 3): the distribution of
+// velocity q at column jv, where jv may lie up to two columns outside
+// 0..nth-1, is that of column jv + nth with direction index mod{i + N_f, N_i}
+// (jv < 0), or of column jv - nth with mod{i - N_f + N_i, N_i} (jv >= nth);
+// i = 1..N_i is the paper's direction index, q = 1 + N_i (k - 1) + (i - 1).
+// Sets the real column and the velocity read there.
+void azimuthal_source(const OrGrid& g, int q, int jv, int& q_src, int& j_src) {
+  q_src = q;
+  j_src = jv;
+  if (jv >= 0 && jv < g.nth) return;
+  int i_dir = q == 0 ? 0 : (q - 1) % NI + 1;
+  int i_src = i_dir;
+  if (jv < 0) {
+    j_src = jv + g.nth;
+    if (q != 0) i_src = paper_mod(i_dir + g.nf, NI);
+  } else {
+    j_src = jv - g.nth;
+    if (q != 0) i_src = paper_mod(i_dir - g.nf + NI, NI);
+  }
+  if (q != 0) q_src = q - i_dir + i_src;
 }
 
 // Macroscopic fields (rho, u_x, u_y, E) of every real node.
@@ -373,24 +399,25 @@ void ghost_macros(const OrGrid& g, int side, double rg1, double rg2, double ct, 
 }
 
 // Fill the padded array for one step: real nodes, the periodic azimuthal
-// ghosts (Sec. II.C, azimuthal boundary condition, with N_f = N_i so that the
-// velocity index is unchanged) and the radial equilibrium ghosts.  Returns the
-// number of ghost nodes whose extrapolated rho or T is not positive.
+// ghosts (Sec. II.C, azimuthal boundary condition: azimuthal_source) and the
+// radial equilibrium ghosts.  Returns the number of ghost nodes whose
+// extrapolated rho or T is not positive.
 int build_padded(const OrGrid& g, const Geometry& geo, const double* f,
                  const std::vector<double>& m, Padded& P) {
+#pragma omp parallel for schedule(static)
   for (int q = 0; q < NQ; ++q)
     for (int i = 0; i < g.nr; ++i)
       for (int j = 0; j < g.nth; ++j) P.at(q, i, j) = f[idx(g, q, i, j)];
   // azimuthal ghosts: i_theta <= 0 takes i_theta + N_theta, i_theta > N_theta
-  // takes i_theta - N_theta.
+  // takes i_theta - N_theta, each with its rotated direction index
   for (int q = 0; q < NQ; ++q)
-    for (int i = 0; i < g.nr; ++i) {
-      P.at(q, i, -1) = P.at(q, i, g.nth - 1);
-      P.at(q, i, -2) = P.at(q, i, g.nth - 2);
-      P.at(q, i, g.nth) = P.at(q, i, 0);
-      P.at(q, i, g.nth + 1) = P.at(q, i, 1);
-    }
-  size_t n = (size_t)g.nr * g.nth;
+    for (int i = 0; i < g.nr; ++i)
+      for (int jv : {-2, -1, g.nth, g.nth + 1}) {
+        int qs, js;
+        azimuthal_source(g, q, jv, qs, js);
+        P.at(q, i, jv) = f[idx(g, qs, i, js)];
+      }
+  const size_t n = (size_t)g.nr * g.nth;
   int bad = 0;
   for (int side = 0; side < 2; ++side) {
     int i0 = side == 0 ? 0 : g.nr - 1;     // row next to the wall
@@ -507,7 +534,11 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
         }
       }
     }
-    std::copy(f_out, f_out + tot, cur.begin());
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < NQ; ++q) {
+      const size_t b = (size_t)q * g.nr * g.nth, e = b + (size_t)g.nr * g.nth;
+      std::copy(f_out + b, f_out + e, cur.begin() + b);
+    }
   }
   if (nsteps == 0) std::copy(cur.begin(), cur.end(), f_out);
   return bad;
@@ -534,9 +565,14 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
       node_f(ii, jj, fl);
       macros(fl, m[0], m[1], m[2], m[3]);
     };
-    // f_q at row ii (possibly a ghost row) and column jj (wrapped)
+    // f_q at row ii (possibly a ghost row) of a real column jj, or at a real
+    // row ii of a column up to two places beyond the ends (azimuthal ghosts)
     auto value = [&](int q, int ii, int jj) -> double {
-      jj = ((jj % g.nth) + g.nth) % g.nth;
+      if (jj < 0 || jj >= g.nth) {
+        int qs, js;
+        azimuthal_source(g, q, jj, qs, js);
+        return f[idx(g, qs, ii, js)];
+      }
       if (ii >= 0 && ii < g.nr) return f[idx(g, q, ii, jj)];
       int side = ii < 0 ? 0 : 1;
       int i0 = side == 0 ? 0 : g.nr - 1, i1 = side == 0 ? 1 : g.nr - 2;
@@ -691,9 +727,12 @@ void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next
       for (int a = 0; a < 4; ++a) gM[a * n + c] += acc[a];
     }
 
-  // (2) convection terms, one velocity plane at a time.
+  // (2) convection terms, one velocity plane at a time.  Across the ends of a
+  // sector a stencil of plane q reads (and so scatters into) other planes of
+  // the same speed, so the threads take one speed each, its planes in turn.
 #pragma omp parallel for schedule(dynamic)
-  for (int q = 0; q < NQ; ++q) {
+  for (int kk = 0; kk <= NK; ++kk)
+  for (int q = kk == 0 ? 0 : 1 + NI * (kk - 1); q < (kk == 0 ? 1 : 1 + NI * kk); ++q) {
     for (int i = 0; i < g.nr; ++i) {
       double r = geo.rr(i);
       for (int j = 0; j < g.nth; ++j) {
@@ -716,8 +755,9 @@ void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next
         for (int s = 0; s < 5; ++s) psi[s] = P.at(q, i, j - 2 + s);
         mwb_grad(Ct, psi, tie_eps, gr);
         for (int s = 0; s < 5; ++s) {
-          int jj = ((j - 2 + s) % g.nth + g.nth) % g.nth;   // periodic wrap
-          lam_out[idx(g, q, i, jj)] += -lam * gr[s];
+          int qs, js;                    // where the stencil's value was read
+          azimuthal_source(g, q, j - 2 + s, qs, js);
+          lam_out[idx(g, qs, i, js)] += -lam * gr[s];
         }
       }
     }
@@ -796,6 +836,85 @@ void or_adjoint_init(const OrGrid* gp, const double* rho, const double* ur, cons
       }
       d_rho[c] = acc[0]; d_ur[c] = acc[1]; d_ut[c] = acc[2]; d_T[c] = acc[3];
     }
+}
+
+// Sec. IV, Eqs. M_relative, M_absolute, D_relative, D_absolute: the moments
+// M_m and the central moments M*_m (velocities relative to the node's flow
+// velocity u) of f, and their departures from equilibrium Delta_m = M_m(f -
+// f^eq) and Delta*_m = M*_m(f - f^eq), f^eq taken at the node's own rho, u,
+// E.  Components in the polar basis (e_r, e_theta) of the node, 12 per kind:
+//   M_2: rr, r theta, theta theta;  M_3: rrr, rr theta, r theta theta,
+//   theta theta theta;  M_{3,1}: r, theta;  M_{4,2}: rr, r theta, theta theta,
+// where M_{3,1} = sum (1/2) f |v|^2 v and M_{4,2} = sum (1/2) f |v|^2 v v.
+// out[((kind * 12 + comp) * nr + i) * nth + j], kind 0 = M, 1 = M*, 2 = Delta,
+// 3 = Delta*.
+// The non-equilibrium fields of one node (i, j): acc[kind][12] as or_noneq.
+static void noneq_node(const OrGrid& g, const Geometry& geo, const double* f, int i, int j,
+                       double acc[4][12]) {
+  double fl[NQ], fe[NQ];
+  for (int q = 0; q < NQ; ++q) fl[q] = f[idx(g, q, i, j)];
+  double rho, ux, uy, E;
+  macros(fl, rho, ux, uy, E);
+  feq_all(rho, ux, uy, E, fe);
+  const double ct = geo.ct[j], st = geo.st[j];
+  const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 12; ++c) acc[a][c] = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    const double vr = vr_of(q, ct, st), vt = vt_of(q, ct, st);
+    for (int kind = 0; kind < 4; ++kind) {
+      const double w = kind < 2 ? fl[q] : fl[q] - fe[q];       // f, or f - f^eq
+      const bool central = kind % 2 == 1;
+      const double a = central ? vr - ur : vr;                  // r component
+      const double b = central ? vt - ut : vt;                  // theta component
+      const double h = 0.5 * (a * a + b * b);                   // |v|^2 / 2
+      double* o = acc[kind];
+      o[0] += w * a * a;  o[1] += w * a * b;  o[2] += w * b * b;
+      o[3] += w * a * a * a;  o[4] += w * a * a * b;  o[5] += w * a * b * b;  o[6] += w * b * b * b;
+      o[7] += w * h * a;  o[8] += w * h * b;
+      o[9] += w * h * a * a;  o[10] += w * h * a * b;  o[11] += w * h * b * b;
+    }
+  }
+}
+
+// Sec. IV, Eqs. M_relative, M_absolute, D_relative, D_absolute: the moments
+// M_m and the central moments M*_m (velocities relative to the node's flow
+// velocity u) of f, and their departures from equilibrium Delta_m = M_m(f -
+// f^eq) and Delta*_m = M*_m(f - f^eq), f^eq taken at the node's own rho, u,
+// E.  Components in the polar basis (e_r, e_theta) of the node, 12 per kind:
+//   M_2: rr, r theta, theta theta;  M_3: rrr, rr theta, r theta theta,
+//   theta theta theta;  M_{3,1}: r, theta;  M_{4,2}: rr, r theta, theta theta,
+// where M_{3,1} = sum (1/2) f |v|^2 v and M_{4,2} = sum (1/2) f |v|^2 v v.
+// out[((kind * 12 + comp) * nr + i) * nth + j], kind 0 = M, 1 = M*, 2 = Delta,
+// 3 = Delta*.
+void or_noneq(const OrGrid* gp, const double* f, double* out) {
+  const OrGrid& g = *gp;
+  Geometry geo(g);
+  const size_t n = (size_t)g.nr * g.nth;
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < g.nr; ++i)
+    for (int j = 0; j < g.nth; ++j) {
+      double acc[4][12];
+      noneq_node(g, geo, f, i, j, acc);
+      const size_t cidx = (size_t)i * g.nth + j;
+      for (int kind = 0; kind < 4; ++kind)
+        for (int c = 0; c < 12; ++c) out[((size_t)kind * 12 + c) * n + cidx] = acc[kind][c];
+    }
+}
+
+// The same at the listed nodes only (nodes[2n] = i, nodes[2n+1] = j):
+// out[(n * 4 + kind) * 12 + comp].
+void or_noneq_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int32_t count,
+                     double* out) {
+  const OrGrid& g = *gp;
+  Geometry geo(g);
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < count; ++n) {
+    double acc[4][12];
+    noneq_node(g, geo, f, nodes[2 * n], nodes[2 * n + 1], acc);
+    for (int kind = 0; kind < 4; ++kind)
+      for (int c = 0; c < 12; ++c) out[((size_t)n * 4 + kind) * 12 + c] = acc[kind][c];
+  }
 }
 
 int or_num_threads() {

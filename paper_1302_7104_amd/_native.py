@@ -20,13 +20,14 @@ ERRORS = {
 WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
 KERNEL_AUTO, KERNEL_NODE, KERNEL_STRIP = 0, 1, 2
 ORDER_DEFAULT, ORDER_XCD, ORDER_PLAIN = 0, 1, 2
+NONEQ_M, NONEQ_MSTAR, NONEQ_DELTA, NONEQ_DSTAR, NONEQ_ALL = 1, 2, 4, 8, 15
 
 #: every symbol include/pclb.h declares
 SYMBOLS = (
     "pclb_cfl_dt", "pclb_create", "pclb_destroy", "pclb_last_error", "pclb_bind",
     "pclb_set_bc", "pclb_init_state", "pclb_step", "pclb_step_into", "pclb_current",
     "pclb_step_count", "pclb_moments", "pclb_moments_of", "pclb_moments_host",
-    "pclb_adjoint_step", "pclb_adjoint_init",
+    "pclb_adjoint_step", "pclb_adjoint_init", "pclb_noneq",
 )
 
 
@@ -43,8 +44,8 @@ class Config(ctypes.Structure):
                 ("n_i", ctypes.c_int32), ("n_f", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("fp64_collision", ctypes.c_int32),
                 ("kernel", ctypes.c_int32),
-                ("strip_chunk", ctypes.c_int32), ("strip_split", ctypes.c_int32),
-                ("strip_order", ctypes.c_int32), ("adjoint_tie", ctypes.c_double)]
+                ("strip_chunk", ctypes.c_int32), ("strip_order", ctypes.c_int32),
+                ("adjoint_tie", ctypes.c_double)]
 
 
 _lib = None
@@ -82,6 +83,7 @@ def lib():
     L.pclb_moments_of.argtypes = [P, _V, _V, _V, _V, _V, _V]
     L.pclb_moments_host.argtypes = [P, _D]
     L.pclb_adjoint_step.argtypes = [P, _V, _V, _V]
+    L.pclb_noneq.argtypes = [P, _V, ctypes.c_int32, _V]
     L.pclb_adjoint_init.argtypes = [P, _V, _V, _V, _V, _V, _V, _V, _V, _V]
     for name in SYMBOLS:
         if name not in ("pclb_cfl_dt", "pclb_destroy", "pclb_last_error"):

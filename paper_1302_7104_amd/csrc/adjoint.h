@@ -19,7 +19,7 @@ struct FeqJac {
   double A0E, A1E, A2E, A3E, A4E;            // dA_n / dE
 };
 
-__device__ inline void feq_jac_setup(const Tables& T, double rho, double ux, double uy, double E,
+PCLB_HD inline void feq_jac_setup(const Tables& T, double rho, double ux, double uy, double E,
                                      FeqJac& J) {
   eq_setup(T, rho, ux, uy, E, J.c);
   J.rho = rho;
@@ -44,7 +44,7 @@ __device__ inline void feq_jac_setup(const Tables& T, double rho, double ux, dou
 
 // G += l * d f^eq_q / d(rho, u_x, u_y, E) for velocity q = (k, d).
 template <int Q>
-__device__ inline void feq_jac_accum(const FeqJac& J, double l, double G[4]) {
+PCLB_HD inline void feq_jac_accum(const FeqJac& J, double l, double G[4]) {
   constexpr int k = k_of(Q), d = d_of(Q);
   double w;
   if (Q == 0) w = 0.0;
@@ -63,7 +63,7 @@ __device__ inline void feq_jac_accum(const FeqJac& J, double l, double G[4]) {
 
 // (G_rho, G_ux, G_uy, G_E) -> cotangents of M = (rho, j_x, j_y, eps) through
 // u = j / rho, E = eps / rho - u^2 / 2.
-__device__ inline void to_moment_cotangent(double rho, double ux, double uy, double E,
+PCLB_HD inline void to_moment_cotangent(double rho, double ux, double uy, double E,
                                            const double G[4], double gM[4]) {
   const double ir = 1.0 / rho;
   gM[0] = G[0] - (G[1] * ux + G[2] * uy) * ir + G[3] * (0.5 * (ux * ux + uy * uy) - E) * ir;
@@ -83,17 +83,23 @@ struct MwbDT {
 };
 using MwbD = MwbDT<double>;
 
-__device__ inline double absv(double x) { return __builtin_fabs(x); }
-__device__ inline float absv(float x) { return __builtin_fabsf(x); }
-__device__ inline double recipv(double x) { return 1.0 / x; }
+PCLB_HD inline double absv(double x) { return __builtin_fabs(x); }
+PCLB_HD inline float absv(float x) { return __builtin_fabsf(x); }
+PCLB_HD inline double recipv(double x) { return 1.0 / x; }
 // the hardware reciprocal (1 ulp): the derivative of an FP32 state's step
 // needs no more
-__device__ inline float recipv(float x) { return __builtin_amdgcn_rcpf(x); }
+PCLB_HD inline float recipv(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;   // host emulation of the device arithmetic (tests only)
+#endif
+}
 
 // In the arithmetic type A: double for FP64 states, float for FP32 states
 // (the tie threshold of FP32 states is far above float rounding).
 template <class A>
-__device__ inline MwbDT<A> mwb_grad_t(A aC, A K, A c, A u1, A u2, A eps) {
+PCLB_HD inline MwbDT<A> mwb_grad_t(A aC, A K, A c, A u1, A u2, A eps) {
   const A zero = 0, one = 1;
   A d1 = c - u1, d2 = u1 - u2;
   const A thr = eps * (absv(c) + absv(u1) + absv(u2));
@@ -115,12 +121,12 @@ __device__ inline MwbDT<A> mwb_grad_t(A aC, A K, A c, A u1, A u2, A eps) {
   return r;
 }
 
-__device__ inline MwbD mwb_grad(double aC, double K, double c, double u1, double u2, double eps) {
+PCLB_HD inline MwbD mwb_grad(double aC, double K, double c, double u1, double u2, double eps) {
   return mwb_grad_t<double>(aC, K, c, u1, u2, eps);
 }
 
 template <class R>
-__device__ inline double fetch_f(const R* __restrict__ f, const R* __restrict__ ghost, int q, int i,
+PCLB_HD inline double fetch_f(const R* __restrict__ f, const R* __restrict__ ghost, int q, int i,
                                  int j, int nr, int nth, size_t plane) {
   if (i < 0) return (double)ghost[ghost_index(0, -1 - i, q, j, nth)];
   if (i >= nr) return (double)ghost[ghost_index(1, i - nr, q, j, nth)];
@@ -128,7 +134,7 @@ __device__ inline double fetch_f(const R* __restrict__ f, const R* __restrict__ 
 }
 
 template <int Q, class Fn>
-__device__ inline void static_for_q(Fn&& fn) {
+PCLB_HD inline void static_for_q(Fn&& fn) {
   if constexpr (Q < NQ) {
     fn(std::integral_constant<int, Q>{});
     static_for_q<Q + 1>(fn);

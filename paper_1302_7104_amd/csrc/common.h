@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 // Every helper below is also compiled for the host, where a CPU emulation of
 // the per-node update runs the same arithmetic for the CPU test-suite.
 #define PCLB_HD __host__ __device__
@@ -82,6 +84,7 @@ __host__ __device__ inline double weight_k_prime(double E) {
 // Everything a step launch needs besides the state buffers.
 struct Tables {
   int32_t nr, nth;
+  int32_t nf;          // theta covers 2 pi nf / 8 (8: the full annulus)
   double dt_dr;        // dt / dr
   double dt_dth;       // dt / dtheta
   double e;            // exp(-dt / tau), computed on the host in double
@@ -89,6 +92,7 @@ struct Tables {
   const double* sth;   // sin(theta_j)
   const double* rinv;  // 1 / r_i, i = 0..nr-1
   const double* wA;    // quadrature weight r_i w_i dr dtheta of row i
+  int32_t n_mixed;     // strips of the strip kernel that contain an octant boundary
 };
 
 // Radial boundary description as the kernels see it.
@@ -155,17 +159,20 @@ PCLB_HD inline double eq_val(const EqCoef& c, int k, int d) {
 // Linear moments of one node, rho, j = sum f v and eps = sum f v^2 (halved at
 // the end), summed per pair of opposite directions (d, d+4), d = 0..3: with
 // sp_k = f_{k,d} + f_{k,d+4} and sm_k = f_{k,d} - f_{k,d+4},
-//   rho_d = sum_k sp_k, j_d = sum_k v_k e_d sm_k, eps_d = sum_k v_k^2 sp_k,
-// the rest velocity counted in rho_0; the four partials are then added in
-// the order d = 0, 1, 2, 3.  Every kernel sums in exactly this order.
-PCLB_HD inline void d4_partial(int d4, double f0, const double* fp, const double* fm, double* P) {
-  double r = f0, jx = 0.0, jy = 0.0, eps = 0.0;
+//   rho_d = sum_k sp_k, j_d = sum_k v_k e_d sm_k, eps_d = sum_k v_k^2 sp_k
+// (e_d's zero components included, so that the same operations run for every
+// d); the four partials are then added in the order d = 0, 1, 2, 3 and the
+// rest velocity last.  Every kernel sums in exactly this order.
+PCLB_HD inline void d4_partial(int d4, const double* fp, const double* fm, double* P) {
+  const double ex = cos_d(d4), ey = sin_d(d4);
+  double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
+#pragma unroll
   for (int k = 1; k <= NK; ++k) {
     const double sp = fp[k - 1] + fm[k - 1];
     const double sm = fp[k - 1] - fm[k - 1];
     r += sp;
-    if (cos_d(d4) != 0.0) jx += (speed(k) * cos_d(d4)) * sm;
-    if (sin_d(d4) != 0.0) jy += (speed(k) * sin_d(d4)) * sm;
+    jx += (speed(k) * ex) * sm;
+    jy += (speed(k) * ey) * sm;
     eps += (speed(k) * speed(k)) * sp;
   }
   P[0] = r;
@@ -175,10 +182,10 @@ PCLB_HD inline void d4_partial(int d4, double f0, const double* fp, const double
 }
 
 // rho, u, E (Eqs. moment1-moment3: E = eps / (2 rho) - u^2 / 2) from the four
-// pair partials P[d][0..3].
-PCLB_HD inline void combine_partials(const double P[4][4], double& rho, double& ux, double& uy,
-                                     double& E) {
-  const double r = ((P[0][0] + P[1][0]) + P[2][0]) + P[3][0];
+// pair partials P[d][0..3] and the rest velocity's value f0.
+PCLB_HD inline void combine_partials(const double P[4][4], double f0, double& rho, double& ux,
+                                     double& uy, double& E) {
+  const double r = (((P[0][0] + P[1][0]) + P[2][0]) + P[3][0]) + f0;
   const double jx = ((P[0][1] + P[1][1]) + P[2][1]) + P[3][1];
   const double jy = ((P[0][2] + P[1][2]) + P[2][2]) + P[3][2];
   const double eps = ((P[0][3] + P[1][3]) + P[2][3]) + P[3][3];
@@ -196,62 +203,119 @@ PCLB_HD inline void node_partials(const double* f, double P[4][4]) {
       fp[k - 1] = f[qidx(k, d4)];
       fm[k - 1] = f[qidx(k, d4 + 4)];
     }
-    d4_partial(d4, d4 == 0 ? f[0] : 0.0, fp, fm, P[d4]);
+    d4_partial(d4, fp, fm, P[d4]);
   }
 }
 
 PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double& uy, double& E) {
   double P[4][4];
   node_partials(f, P);
-  combine_partials(P, rho, ux, uy, E);
+  combine_partials(P, f[0], rho, ux, uy, E);
 }
 
-// Relaxed values of the opposite pair (k, d) and (k, d + 4), d = 0..3:
-// f^eq + (f - f^eq) e written as e f + (1 - e) f^eq, with f^eq = rho F_k P(+-w)
-// and P split into its even and odd parts in w = v_k pd, pd = u . e_d (the
-// caller passes c.p[d], or its negative to swap the roles of the pair).  In
-// double; the result is rounded once to the state type R.
+// Coefficients of the analytic relaxation (Eq. operator1_new) of one node:
+// the relaxed value e f + (1 - e) f^eq of velocity (k, d) with
+// f^eq = rho F_k P(w), w = v_k p_d, p_d = u . e_d, written from the powers of
+// p_d so that the four speeds of a direction share them:
+//   (1 - e) f^eq_{k,d}    = s_k (even + odd),  (1 - e) f^eq_{k,d+4} = s_k (even - odd),
+//   even = A0 + v_k^2 (A2 p^2) + v_k^4 (A4 p^4),  odd = v_k (A1 p) + v_k^3 (A3 p^3),
+// s_k = (1 - e) rho F_k; the rest velocity's share is s_0 = (1 - e) rho F_0 A0.
+struct RelaxCoef {
+  double s[NK + 1];
+  double A0;
+  double b[4][4];      // per direction pair d = 0..3: A1 p, A2 p^2, A3 p^3, A4 p^4
+};
+
+PCLB_HD inline void relax_setup(const EqCoef& c, double one_m_e, RelaxCoef& rc) {
+  rc.s[0] = one_m_e * (c.rF[0] * c.A0);
+#pragma unroll
+  for (int k = 1; k <= NK; ++k) rc.s[k] = one_m_e * c.rF[k];
+  rc.A0 = c.A0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const double p = c.p[d], p2 = p * p;
+    rc.b[d][0] = c.A1 * p;
+    rc.b[d][1] = c.A2 * p2;
+    rc.b[d][2] = c.A3 * (p2 * p);
+    rc.b[d][3] = c.A4 * (p2 * p2);
+  }
+}
+
+// Relaxed values of the opposite pair (k, d) and (k, d + 4) from the pair's
+// coefficients b = b[d] with the odd ones (b[0], b[2]) multiplied by sg (+1;
+// -1 hands the pair over in the order (d + 4, d)).  In double.
+template <int K>
+PCLB_HD inline void relax_pair(double s, double A0, double b0, double b1, double b2, double b3,
+                               double e, double fp, double fm, double& rp, double& rm) {
+  constexpr double v = speed(K), v2 = v * v, v3 = v2 * v, v4 = v2 * v2;
+  const double ev = fma(v4, b3, fma(v2, b1, A0));
+  const double od = fma(v3, b2, v * b0);
+  const double t = s * ev;
+  rp = fma(fp, e, fma(s, od, t));
+  rm = fma(fm, e, fma(-s, od, t));
+}
+
 template <class R>
-PCLB_HD inline void relax_pair(const EqCoef& c, double e, double one_m_e, int k, double pd,
-                               double fp, double fm, R& rp, R& rm) {
-  const double w = speed(k) * pd;
-  const double w2 = w * w;
-  const double ev = c.A0 + w2 * (c.A2 + w2 * c.A4);
-  const double od = w * (c.A1 + w2 * c.A3);
-  const double s = one_m_e * c.rF[k];
-  const double gp = s * (ev + od), gm = s * (ev - od);
-  rp = (R)fma(fp, e, gp);
-  rm = (R)fma(fm, e, gm);
+PCLB_HD inline R relax_rest(double s0, double e, double f0) {
+  return (R)fma(f0, e, s0);
 }
 
-template <class R>
-PCLB_HD inline R relax_rest(const EqCoef& c, double e, double one_m_e, double f0) {
-  const double g = one_m_e * (c.rF[0] * c.A0);
-  return (R)fma(f0, e, g);
+// Upwind sides.  The radial and azimuthal components of direction d at angle
+// theta are v_k cos(d pi/4 - theta) and v_k sin(d pi/4 - theta); a velocity is
+// upwind-backward (its stencil lies at lower index) where its component is
+// >= 0.  Inside the octant (m pi/4, (m+1) pi/4] of theta the pattern of signs
+// depends only on d - m: relative to the octant, directions 7, 0, 1, 2 are
+// radially backward and 1, 2, 3, 4 azimuthally backward.  The octant of
+// column j follows from exact integer arithmetic, theta_j = (j+1) 2 pi / nth,
+// so the side is exact even at the columns on the axes theta = m pi/4, where
+// one component of four directions vanishes and its computed value is
+// rounding noise: such a column takes the sides of the octant below it (the
+// limit of the signs as theta approaches the axis from below).  The term of
+// that component has |C| ~ 1e-17 there, so the choice moves no result
+// beyond that size.
+PCLB_HD inline int octant_of(int j, int nth, int nf) {
+  // theta_j = (j+1) dtheta with dtheta = 2 pi nf / (8 nth): the octant m
+  // with theta_j in (m pi/4, (m+1) pi/4]
+  return (int)(((long long)nf * (j + 1) - 1) / nth);
 }
 
-// Direction geometry of one theta column: for each direction d, the sign of
-// v_r and v_theta (upwind side: bit d set = backward, i.e. v >= 0) and, per
-// d mod 4, |v_r| dt/dr and |v_theta| dt/dtheta per unit speed.  The Courant
-// numbers of velocity (k, d) are v_k * ar[d mod 4] and v_k * at[d mod 4] / r.
+// Azimuthal boundary condition of a sector 0 < theta <= 2 pi nf / 8 (Sec.
+// II.C, Fig. 3): a ghost column before the first real one holds the values
+// of the column nth places later with the direction index advanced by nf,
+// a ghost column after the last holds those nth places earlier with it
+// moved back by nf (8 - nf modulo 8).  rot_q returns the velocity whose
+// plane is read: speed unchanged, direction d -> (d + s) mod 8; the rest
+// velocity is unchanged.  With nf = 8 both rotations are the identity.
+PCLB_HD inline int rot_q(int q, int s) {
+  return q == 0 ? 0 : 1 + ((q - 1) & ~7) + (((q - 1) + s) & 7);
+}
+PCLB_HD inline unsigned rot8(unsigned bits, int m) {
+  return ((bits << m) | (bits >> (8 - m))) & 0xffu;
+}
+constexpr unsigned RBACK_OCT0 = 0x87u;   // relative directions 0, 1, 2, 7
+constexpr unsigned TBACK_OCT0 = 0x1eu;   // relative directions 1, 2, 3, 4
+PCLB_HD inline unsigned rback_bits(int oct) { return rot8(RBACK_OCT0, oct); }
+PCLB_HD inline unsigned tback_bits(int oct) { return rot8(TBACK_OCT0, oct); }
+
+// Direction geometry of one theta column: for each direction d, the upwind
+// sides (bit d set = backward) and, per d mod 4, |v_r| dt/dr and
+// |v_theta| dt/dtheta per unit speed.  The Courant numbers of velocity (k, d)
+// are v_k * ar[d mod 4] and v_k * at[d mod 4] / r.
 template <class R> struct DirGeom {
   R ar[4], at[4];
   unsigned rback, tback;
 };
 template <class R>
-PCLB_HD inline void dir_geometry(double ct, double st, double dt_dr, double dt_dth, DirGeom<R>& g) {
-  g.rback = 0;
-  g.tback = 0;
+PCLB_HD inline void dir_geometry(double ct, double st, int oct, double dt_dr, double dt_dth,
+                                 DirGeom<R>& g) {
+  g.rback = rback_bits(oct);
+  g.tback = tback_bits(oct);
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
+  for (int d = 0; d < 4; ++d) {
     const double vr = cos_d(d) * ct + sin_d(d) * st;     // v_r / v_k
     const double vt = sin_d(d) * ct - cos_d(d) * st;     // v_theta / v_k
-    if (vr >= 0.0) g.rback |= 1u << d;
-    if (vt >= 0.0) g.tback |= 1u << d;
-    if (d < 4) {
-      g.ar[d] = (R)(fabs(vr) * dt_dr);
-      g.at[d] = (R)(fabs(vt) * dt_dth);
-    }
+    g.ar[d] = (R)(fabs(vr) * dt_dr);
+    g.at[d] = (R)(fabs(vt) * dt_dth);
   }
 }
 // |C| and |C|(1 - |C|) from the speed and the per-unit-speed factor.
@@ -301,22 +365,31 @@ PCLB_HD inline R mwb_term(R absC, R K, R c, R u1, R u2) {
 }
 
 // rel - T_r - T_theta for one velocity from the radial differences (d1r, d2r)
-// with (aCr, Kr) and the azimuthal ones (d1t, d2t) with (aCt, Kt).
+// with (aCr, Kr) and the azimuthal ones (d1t, d2t) with (aCt, Kt).  The two
+// MWB terms are formed in the state type (each is a Courant number times an
+// upwind difference, far smaller than f); they are subtracted from the relaxed
+// value in double, and the new f is rounded once to the state type.  (Four
+// float operations at the size of f would round four times.)
 template <class R>
-PCLB_HD inline R mwb_update_d(R rel, R aCr, R Kr, R d1r, R d2r, R aCt, R Kt, R d1t, R d2t) {
-  const R lr = mwb_lim<R>(d1r, d2r);
-  const R lt = mwb_lim<R>(d1t, d2t);
-  R res = rel - aCr * d1r;
-  res = res - Kr * lr;
-  res = res - aCt * d1t;
-  res = res - Kt * lt;
-  return res;
+PCLB_HD inline R mwb_update_d(double rel, R aCr, R Kr, R d1r, R d2r, R aCt, R Kt, R d1t, R d2t) {
+  const R tr = aCr * d1r + Kr * mwb_lim<R>(d1r, d2r);
+  const R tt = aCt * d1t + Kt * mwb_lim<R>(d1t, d2t);
+  return (R)((rel - (double)tr) - (double)tt);
 }
 
 // The same from the centre value c and the upwind neighbours.
 template <class R>
-PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, R u1t, R u2t) {
+PCLB_HD inline R mwb_update(double rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, R u1t, R u2t) {
   return mwb_update_d<R>(rel, aCr, Kr, c - u1r, u1r - u2r, aCt, Kt, c - u1t, u1t - u2t);
+}
+
+// Compile-time loop over the speeds k = K..NK.
+template <int K, class Fn>
+PCLB_HD inline void for_k(Fn&& fn) {
+  if constexpr (K <= NK) {
+    fn(std::integral_constant<int, K>{});
+    for_k<K + 1>(fn);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -326,28 +399,31 @@ PCLB_HD inline R mwb_update(R rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, 
 // put(q, value) receives f_q at t + dt as soon as it is computed (so that a
 // kernel can store it at once instead of holding all 33 results).
 template <class R, class RowFn, class ColFn, class PutFn>
-PCLB_HD inline void node_update_put(const Tables& T, int i, double ct, double st, const R* fc,
-                                    RowFn row, ColFn col, PutFn put) {
+PCLB_HD inline void node_update_put(const Tables& T, int i, int j, const R* fc, RowFn row,
+                                    ColFn col, PutFn put) {
+  const double ct = T.cth[j], st = T.sth[j];
   double fd[NQ];
   for (int q = 0; q < NQ; ++q) fd[q] = (double)fc[q];
   double rho, ux, uy, E;
   node_macros(fd, rho, ux, uy, E);
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
-  const double e = T.e, ome = 1.0 - T.e;
-  put(0, relax_rest<R>(ec, e, ome, fd[0]));       // rest velocity: no convection
+  RelaxCoef rc;
+  relax_setup(ec, 1.0 - T.e, rc);
+  const double e = T.e;
+  put(0, relax_rest<R>(rc.s[0], e, fd[0]));       // rest velocity: no convection
   DirGeom<R> G;
-  dir_geometry(ct, st, T.dt_dr, T.dt_dth, G);
+  dir_geometry(ct, st, octant_of(j, T.nth, T.nf), T.dt_dr, T.dt_dth, G);
   const R rinv = (R)T.rinv[i];
   R atr[4];
   for (int d = 0; d < 4; ++d) atr[d] = G.at[d] * rinv;
-#pragma unroll
-  for (int k = 1; k <= NK; ++k) {
+  for_k<1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
 #pragma unroll
     for (int d4 = 0; d4 < 4; ++d4) {
-      R rel[2];
-      relax_pair<R>(ec, e, ome, k, ec.p[d4], fd[qidx(k, d4)], fd[qidx(k, d4 + 4)], rel[0],
-                    rel[1]);
+      double rel[2];
+      relax_pair<k>(rc.s[k], rc.A0, rc.b[d4][0], rc.b[d4][1], rc.b[d4][2], rc.b[d4][3], e,
+                       fd[qidx(k, d4)], fd[qidx(k, d4 + 4)], rel[0], rel[1]);
       R aCr, Kr, aCt, Kt;
       courant<R>((R)speed(k), G.ar[d4], aCr, Kr);
       courant<R>((R)speed(k), atr[d4], aCt, Kt);
@@ -361,14 +437,14 @@ PCLB_HD inline void node_update_put(const Tables& T, int i, double ct, double st
                              col(q, sc), col(q, 2 * sc)));
       }
     }
-  }
+  });
 }
 
 // The same with the results in res[0..NQ-1].
 template <class R, class RowFn, class ColFn>
-PCLB_HD inline void node_update(const Tables& T, int i, double ct, double st, const R* fc, RowFn row,
-                                ColFn col, R* res) {
-  node_update_put<R>(T, i, ct, st, fc, row, col, [&](int q, R v) { res[q] = v; });
+PCLB_HD inline void node_update(const Tables& T, int i, int j, const R* fc, RowFn row, ColFn col,
+                                R* res) {
+  node_update_put<R>(T, i, j, fc, row, col, [&](int q, R v) { res[q] = v; });
 }
 
 // Ghost layers of one wall and column (Sec. II.C, radial boundary condition):

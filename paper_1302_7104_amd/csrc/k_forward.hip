@@ -46,6 +46,35 @@ __device__ inline R fetch(const R* __restrict__ f, const R* __restrict__ ghost, 
   return f[q * plane + (size_t)i * nth + j];
 }
 
+template <class R>
+__device__ inline void node_step_at(const Tables& T, const R* __restrict__ f, R* __restrict__ out,
+                                    const R* __restrict__ ghost, int i, int j) {
+  const int nr = T.nr, nth = T.nth;
+  const size_t plane = (size_t)nr * nth;
+  const size_t c0 = (size_t)i * nth + j;
+  R fc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) fc[q] = f[q * plane + c0];
+  auto row = [&](int q, int di) { return fetch(f, ghost, q, i + di, j, nr, nth, plane); };
+  // theta neighbours; across the ends of a sector the direction index rotates
+  const int s_lo = T.nf & 7, s_hi = (8 - T.nf) & 7;
+  auto col = [&](int q, int dj) {
+    int t = j + dj, qq = q;
+    if (t < 0) {
+      t += nth;
+      qq = rot_q(q, s_lo);
+    } else if (t >= nth) {
+      t -= nth;
+      qq = rot_q(q, s_hi);
+    }
+    return f[qq * plane + (size_t)i * nth + t];
+  };
+  // each result is stored as soon as it is computed: holding all 33 (with the
+  // centre values and the neighbours in flight) kept the kernel at one wave
+  // per SIMD
+  node_update_put<R>(T, i, j, fc, row, col, [&](int q, R v) { out[q * plane + c0] = v; });
+}
+
 // Three waves per SIMD: the FP64 kernel then keeps 168 VGPRs and spills 24
 // of them to scratch, which is still faster than two waves without spills
 // (6.3 against 6.8 ms per step at 4096 x 8192; four waves: 8.9 ms).
@@ -54,25 +83,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
 step_node_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
                  const R* __restrict__ ghost) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = blockIdx.y;
   if (j >= T.nth) return;
-  const int nr = T.nr, nth = T.nth;
-  const size_t plane = (size_t)nr * nth;
-  const size_t c0 = (size_t)i * nth + j;
-  R fc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) fc[q] = f[q * plane + c0];
-  auto row = [&](int q, int di) { return fetch(f, ghost, q, i + di, j, nr, nth, plane); };
-  auto col = [&](int q, int dj) {
-    int t = j + dj;
-    t = t < 0 ? t + nth : (t >= nth ? t - nth : t);
-    return f[q * plane + (size_t)i * nth + t];
-  };
-  // each result is stored as soon as it is computed: holding all 33 (with the
-  // centre values and the neighbours in flight) kept the kernel at one wave
-  // per SIMD
-  node_update_put<R>(T, i, T.cth[j], T.sth[j], fc, row, col,
-                     [&](int q, R v) { out[q * plane + c0] = v; });
+  node_step_at<R>(T, f, out, ghost, blockIdx.y, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,6 +135,73 @@ __global__ void __launch_bounds__(256) fields_kernel(Tables T, const R* __restri
   if (ur) ur[c0] = ux * ct + uy * st;
   if (ut) ut[c0] = -ux * st + uy * ct;
   if (Tt) Tt[c0] = E;
+}
+
+// ---------------------------------------------------------------------------
+// Non-equilibrium fields of Sec. IV (Eqs. M_relative, M_absolute, D_relative,
+// D_absolute): per node the moments M_m and central moments M*_m of f and
+// their departures from equilibrium Delta_m = M_m(f - f^eq), Delta*_m =
+// M*_m(f - f^eq), m in {2, 3, (3,1), (4,2)}, in the node's polar basis, 12
+// components per kind (rr, r theta, theta theta; rrr, rr theta, r theta theta,
+// theta theta theta; r, theta; rr, r theta, theta theta).  f^eq is summed from
+// the discrete equilibrium of the node's rho, u, E.  All in double.  The kinds
+// selected by the bit mask go to out in the order M, M*, Delta, Delta*.
+template <class R>
+__global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restrict__ f, int kinds,
+                                                    double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  const size_t c0 = (size_t)i * T.nth + j;
+  double fl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) fl[q] = (double)f[q * plane + c0];
+  double rho, ux, uy, E;
+  node_macros(fl, rho, ux, uy, E);
+  EqCoef ec;
+  eq_setup(T, rho, ux, uy, E, ec);
+  const double ct = T.cth[j], st = T.sth[j];
+  const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
+  double acc[4][12];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[a][c] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double feq = q == 0 ? ec.rF[0] * ec.A0 : eq_val(ec, k_of(q), d_of(q));
+    const double vr = vx_q(q) * ct + vy_q(q) * st, vt = -vx_q(q) * st + vy_q(q) * ct;
+#pragma unroll
+    for (int kind = 0; kind < 4; ++kind) {
+      const double w = kind < 2 ? fl[q] : fl[q] - feq;
+      const double a = (kind & 1) ? vr - ur : vr;
+      const double b = (kind & 1) ? vt - ut : vt;
+      const double h = 0.5 * (a * a + b * b);
+      double* o = acc[kind];
+      const double wa = w * a, wb = w * b, waa = wa * a, wab = wa * b, wbb = wb * b;
+      o[0] += waa;
+      o[1] += wab;
+      o[2] += wbb;
+      o[3] += waa * a;
+      o[4] += waa * b;
+      o[5] += wab * b;
+      o[6] += wbb * b;
+      o[7] += h * wa;
+      o[8] += h * wb;
+      o[9] += h * waa;
+      o[10] += h * wab;
+      o[11] += h * wbb;
+    }
+  }
+  int slot = 0;
+#pragma unroll
+  for (int kind = 0; kind < 4; ++kind) {
+    if (!((kinds >> kind) & 1)) continue;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[((size_t)slot * 12 + c) * plane + c0] = acc[kind][c];
+    ++slot;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -265,6 +344,13 @@ hipError_t launch_zero_int(int* p, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class R>
+hipError_t launch_noneq(const Tables& T, const void* f, int kinds, double* out, hipStream_t s) {
+  dim3 grid((T.nth + 255) / 256, T.nr);
+  hipLaunchKernelGGL(noneq_kernel<R>, grid, dim3(256), 0, s, T, (const R*)f, kinds, out);
+  return hipGetLastError();
+}
+
 int diag_blocks() { return 1024; }
 int diag_slots() { return DIAG_SLOTS; }
 
@@ -286,7 +372,8 @@ hipError_t launch_diag(const Tables& T, const void* f, double* partial, double s
                                      const double*, void*, int*, hipStream_t);                    \
   template hipError_t launch_fields<R>(const Tables&, const void*, double*, double*, double*,     \
                                        double*, hipStream_t);                                     \
-  template hipError_t launch_diag<R>(const Tables&, const void*, double*, double, double*, hipStream_t);
+  template hipError_t launch_diag<R>(const Tables&, const void*, double*, double, double*, hipStream_t); \
+  template hipError_t launch_noneq<R>(const Tables&, const void*, int, double*, hipStream_t);
 PCLB_INST(float)
 PCLB_INST(double)
 #undef PCLB_INST

@@ -21,7 +21,10 @@
 // pair as (backward member, forward member) and picks the planes it reads and
 // writes with scalar offsets, so that its hot loop has no per-lane selects.
 // Strips where a sign changes inside the strip run the same code with lane
-// selects ("mixed").  Both round exactly like the node kernel.
+// selects ("mixed").  Both round exactly like the node kernel.  The upwind
+// sides are those of the column's octant (octant_of), so a strip is uniform
+// exactly when all its columns lie in one octant: when n_theta is a multiple
+// of 512 every strip is.
 #include <type_traits>
 
 #include "common.h"
@@ -183,20 +186,24 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
       f1[k - 1] = (double)(back(v1) ? C[v1] : A[v1]);
     }
     double* Pd = P[O::D40 + pl];
-    d4_partial(O::D40 + pl, (W == 0 && pl == 0) ? (double)r0 : 0.0, f0, f1, Pd);
+    d4_partial(O::D40 + pl, f0, f1, Pd);
     if constexpr (UNI) {            // f0 - f1 was taken with the members swapped
       Pd[1] *= RL.sg[pl];
       Pd[2] *= RL.sg[pl];
     }
   }
+  double rest = (double)r0;            // wave 0's; the others read it from LDS
   if constexpr (NSPLIT > 1) {
-    // lds[(d * 4 + a) * 64 + lane], double-buffered by row parity
-    double* buf = lds + (i & 1) * (16 * 64);
+    // lds[(d * 4 + a) * 64 + lane] and the rest velocity at lds[16 * 64 + lane],
+    // double-buffered by row parity
+    double* buf = lds + (i & 1) * (17 * 64);
 #pragma unroll
     for (int pl = 0; pl < O::D4N; ++pl)
 #pragma unroll
       for (int a = 0; a < 4; ++a) buf[((O::D40 + pl) * 4 + a) * 64 + lane] = P[O::D40 + pl][a];
+    if constexpr (W == 0) buf[16 * 64 + lane] = rest;
     __syncthreads();
+    if constexpr (W != 0) rest = buf[16 * 64 + lane];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
       if (d >= O::D40 && d < O::D40 + O::D4N) continue;
@@ -205,9 +212,11 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
     }
   }
   double rho, ux, uy, E;
-  combine_partials(P, rho, ux, uy, E);
+  combine_partials(P, rest, rho, ux, uy, E);
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
+  RelaxCoef rc;
+  relax_setup(ec, X.ome, rc);
   // 1/r of this row from lane (i - i_begin) of rinv_lane: a table load here
   // would be waited for in order behind every look-ahead load and store in
   // flight
@@ -215,7 +224,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   const uint32_t ovoff = X.store ? (uint32_t)(i * X.nth) * 4u + X.col4 : OOB;
   const uint32_t vb = row_off(X, i + NS - 2, moreN), vf = row_off(X, i + NS, moreN);
   if constexpr (W == 0) {            // rest velocity: relaxation only, one row ahead
-    const float res = relax_rest<float>(ec, X.e, X.ome, (double)r0);
+    const float res = relax_rest<float>(rc.s[0], X.e, (double)r0);
     store_slot<1>(X, 0, ovoff, res);
     r0 = load_slot<EDGE, 1>(X, 0, 0, i + 1, row_off(X, i + 1, more), more);
   }
@@ -227,13 +236,15 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
     const bool b0 = back(v0), b1 = back(v1);
     const float c0 = b0 ? C[v0] : A[v0];
     const float c1 = b1 ? C[v1] : A[v1];
-    float rel[2];
-    const double pd = UNI ? RL.sg[pl] * ec.p[d4] : ec.p[d4];
-    relax_pair<float>(ec, X.e, X.ome, k, pd, (double)c0, (double)c1, rel[0], rel[1]);
+    double rel[2];
+    // with the members swapped the odd coefficients change sign, exactly
+    const double sg = UNI ? RL.sg[pl] : 1.0;
+    relax_pair<k>(rc.s[k], rc.A0, sg * rc.b[d4][0], rc.b[d4][1], sg * rc.b[d4][2],
+                         rc.b[d4][3], X.e, (double)c0, (double)c1, rel[0], rel[1]);
     float aCr, Kr, aCt, Kt;
     courant<float>((float)speed(k), G.ar[d4], aCr, Kr);
     courant<float>((float)speed(k), G.at[d4] * rinv, aCt, Kt);
-    auto one = [&](auto vv, bool bk, float c, float rl) {
+    auto one = [&](auto vv, bool bk, float c, double rl) {
       constexpr int v = decltype(vv)::value;
       constexpr int h = O::h_of(v);
       // azimuthal differences.  Uniform waves: d1 from the upwind lane (the
@@ -448,7 +459,7 @@ template <int NSPLIT, bool MIXED>
 __global__ void __launch_bounds__(WAVE * NSPLIT)
 step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out,
                   const float* __restrict__ ghost, int chunk_rows, int n_strips, int xcd_order) {
-  __shared__ double lds[NSPLIT > 1 ? 2 * 16 * 64 : 1];
+  __shared__ double lds[NSPLIT > 1 ? 2 * 17 * 64 : 1];
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x >> 6;                     // wave within the group
   const int w_item = work_item(xcd_order);
@@ -496,7 +507,7 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   X.e = T.e;
   X.ome = 1.0 - T.e;
   DirGeom<float> G;
-  dir_geometry(T.cth[X.col], T.sth[X.col], T.dt_dr, T.dt_dth, G);
+  dir_geometry(T.cth[X.col], T.sth[X.col], octant_of(X.col, nth, T.nf), T.dt_dr, T.dt_dth, G);
   if constexpr (NSPLIT == 1) {
     strip_wave<1, 0, MIXED>(T, X, G, i_begin, i_end, lds);
   } else if constexpr (NSPLIT == 2) {
@@ -516,7 +527,10 @@ bool strip_supported(const Tables& T) {
   // plus the lane offset, kept below 9 planes) must stay below 2^31, the OOB
   // marker; the lanes of one strip must be distinct columns
   const double plane_bytes = 4.0 * T.nr * (double)T.nth;
-  return std::is_same<R, float>::value && T.nth >= WAVE && 9.0 * plane_bytes < 2147483647.0;
+  // the strip kernel wraps theta without rotating the velocity index: full
+  // annulus only
+  return std::is_same<R, float>::value && T.nf == 8 && T.nth >= WAVE &&
+         9.0 * plane_bytes < 2147483647.0;
 }
 
 int strip_default_chunk(const Tables& T) {
@@ -527,13 +541,29 @@ int strip_default_chunk(const Tables& T) {
   return chunk;
 }
 
+// Strips whose lanes' columns (taken modulo n_theta, as the kernel takes
+// them, so that a ragged last strip counts its wrapped lanes) lie in more
+// than one octant (host side): with the upwind sides taken from the octants
+// every other strip is uniform.
+int strip_mixed_count(int nth, int nf) {
+  int n = 0;
+  for (int j0 = 0; j0 < nth; j0 += WAVE) {
+    const int oct = octant_of(j0, nth, nf);
+    for (int l = 1; l < WAVE; ++l)
+      if (octant_of((j0 + l) % nth, nth, nf) != oct) {
+        ++n;
+        break;
+      }
+  }
+  return n;
+}
+
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
                              const StripTune& tune, hipStream_t s) {
   if (!strip_supported<R>(T)) return hipErrorNotSupported;
   const int chunk_rows = tune.chunk > 0 ? tune.chunk : strip_default_chunk(T);
   if (chunk_rows > WAVE) return hipErrorInvalidValue;   // 1/r of a chunk is held one row per lane
-  const int split = tune.split > 0 ? tune.split : 2;
   const int order = tune.order >= 0 ? (tune.order ? 1 : 0) : 1;
   const int strips = n_strips(T.nth);
   const int chunks = (T.nr + chunk_rows - 1) / chunk_rows;
@@ -541,38 +571,19 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
   const float* fi = (const float*)f;
   float* fo = (float*)out;
   const float* gh = (const float*)ghost;
-  // two launches over the same grid: strips whose waves are all uniform,
-  // then the others (each block of one launch returns at once in the other)
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    if (split == 1) {
-      if (m == 0)
-        hipLaunchKernelGGL((step_strip_kernel<1, false>), dim3(blocks), dim3(WAVE), 0, s, T, fi, fo,
-                           gh, chunk_rows, strips, order);
-      else
-        hipLaunchKernelGGL((step_strip_kernel<1, true>), dim3(blocks), dim3(WAVE), 0, s, T, fi, fo,
-                           gh, chunk_rows, strips, order);
-    } else if (split == 2) {
-      if (m == 0)
-        hipLaunchKernelGGL((step_strip_kernel<2, false>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi,
-                           fo, gh, chunk_rows, strips, order);
-      else
-        hipLaunchKernelGGL((step_strip_kernel<2, true>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi,
-                           fo, gh, chunk_rows, strips, order);
-    } else if (split == 4) {
-      if (m == 0)
-        hipLaunchKernelGGL((step_strip_kernel<4, false>), dim3(blocks), dim3(4 * WAVE), 0, s, T, fi,
-                           fo, gh, chunk_rows, strips, order);
-      else
-        hipLaunchKernelGGL((step_strip_kernel<4, true>), dim3(blocks), dim3(4 * WAVE), 0, s, T, fi,
-                           fo, gh, chunk_rows, strips, order);
-    } else {
-      return hipErrorInvalidValue;
-    }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  // strips whose waves are all uniform, then (if any strip straddles an
+  // octant boundary, or has its halo columns apart) the others, in a second
+  // launch over the same grid in which the uniform strips return at once
+  hipLaunchKernelGGL((step_strip_kernel<2, false>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo,
+                     gh, chunk_rows, strips, order);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (T.n_mixed > 0 || T.nth % 2 != 0) {
+    hipLaunchKernelGGL((step_strip_kernel<2, true>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo,
+                       gh, chunk_rows, strips, order);
+    e = hipGetLastError();
   }
-  return hipSuccess;
+  return e;
 }
 
 template bool strip_supported<float>(const Tables&);

@@ -16,9 +16,10 @@ hipError_t launch_step_node(const Tables& T, const void* f, void* out, const voi
 // them changes the results.
 struct StripTune {
   int chunk = 0;   // rows marched by one workgroup
-  int split = 0;   // wavefronts sharing one strip (1, 2 or 4)
   int order = -1;  // 1: XCD-contiguous workgroup order, 0: plain order
 };
+// Strips of the strip kernel that contain an octant boundary (host side).
+int strip_mixed_count(int nth, int nf);
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
                              const StripTune& tune, hipStream_t s);
@@ -34,6 +35,8 @@ template <class R>
 hipError_t launch_diag(const Tables& T, const void* f, double* partial, double step, double* out,
                        hipStream_t s);
 hipError_t launch_zero_int(int* p, hipStream_t s);
+template <class R>
+hipError_t launch_noneq(const Tables& T, const void* f, int kinds, double* out, hipStream_t s);
 int diag_blocks();
 int diag_slots();
 

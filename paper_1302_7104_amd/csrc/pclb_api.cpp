@@ -55,6 +55,9 @@ int hip_fail(pclb_ctx* c, hipError_t e, const char* where) {
   return fail(c, PCLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// theta increment of Sec. II.C: 2 pi n_f / (n_i n_theta) with n_i = 8
+double sector_dth(const pclb_config* c) { return 2.0 * PI * c->n_f / (8.0 * c->n_theta); }
+
 int validate(const pclb_config* c, std::string& why) {
   if (!c) { why = "null config"; return PCLB_EINVAL; }
   if (!(c->r1 > 0.0) || !(c->r2 > c->r1)) { why = "need 0 < r1 < r2"; return PCLB_EINVAL; }
@@ -64,16 +67,15 @@ int validate(const pclb_config* c, std::string& why) {
   if (!(c->tau > 0.0) || !std::isfinite(c->tau)) { why = "tau must be > 0"; return PCLB_EINVAL; }
   if (!(c->dt > 0.0) || !std::isfinite(c->dt)) { why = "dt must be > 0"; return PCLB_EINVAL; }
   if (c->n_i != 8) { why = "only the octagon model (n_i = 8) is built"; return PCLB_EINVAL; }
-  if (c->n_f != 8) { why = "only the full annulus (n_f = n_i = 8) is built"; return PCLB_EINVAL; }
+  if (c->n_f < 1 || c->n_f > 8) { why = "n_f must be in 1..8 (theta covers 2 pi n_f / 8)"; return PCLB_EINVAL; }
   if (c->precision != 32 && c->precision != 64) { why = "precision must be 32 or 64"; return PCLB_EINVAL; }
   if (c->fp64_collision != 1) {
     why = "fp64_collision must be 1 (float collision is not offered: it loses accuracy and no time)";
     return PCLB_EINVAL;
   }
   if (c->kernel < 0 || c->kernel > 2) { why = "unknown kernel selection"; return PCLB_EINVAL; }
-  if (c->strip_chunk < 0 || c->strip_chunk > 64 || c->strip_split < 0 || c->strip_split == 3 ||
-      c->strip_split > 4 || c->strip_order < 0 || c->strip_order > 2) {
-    why = "strip launch shape out of range (strip_chunk 0-64, strip_split 0, 1, 2 or 4, strip_order 0-2)";
+  if (c->strip_chunk < 0 || c->strip_chunk > 64 || c->strip_order < 0 || c->strip_order > 2) {
+    why = "strip launch shape out of range (strip_chunk 0-64, strip_order 0-2)";
     return PCLB_EINVAL;
   }
   if (!(c->adjoint_tie >= 0.0) || !(c->adjoint_tie < 1e-2)) {
@@ -81,7 +83,7 @@ int validate(const pclb_config* c, std::string& why) {
     return PCLB_EINVAL;
   }
   double dr = (c->r2 - c->r1) / (c->n_r - 1);
-  double dth = 2.0 * PI / c->n_theta;
+  double dth = sector_dth(c);
   double vmax = speed(NK);
   double cr = vmax * c->dt / dr, ct = vmax * c->dt / (c->r1 * dth);
   if (cr > 1.0 || ct > 1.0) {
@@ -94,29 +96,32 @@ int validate(const pclb_config* c, std::string& why) {
 }
 
 template <class R>
-hipError_t do_step(pclb_ctx* c, const void* in, void* out) {
-  hipError_t e = launch_ghost<R>(c->T, c->bc, in, c->d_ghost, c->stream);
+hipError_t do_step(pclb_ctx* c, const void* in, void* out, void* ghost) {
+  hipError_t e = launch_ghost<R>(c->T, c->bc, in, ghost, c->stream);
   if (e != hipSuccess) return e;
   int kern = c->cfg.kernel;
   if (kern == PCLB_KERNEL_STRIP || (kern == PCLB_KERNEL_AUTO && strip_supported<R>(c->T)))
     if (strip_supported<R>(c->T))
-      return launch_step_strip<R>(c->T, in, out, c->d_ghost, c->tune, c->stream);
-  return launch_step_node<R>(c->T, in, out, c->d_ghost, c->stream);
+      return launch_step_strip<R>(c->T, in, out, ghost, c->tune, c->stream);
+  return launch_step_node<R>(c->T, in, out, ghost, c->stream);
 }
 
-hipError_t step_once(pclb_ctx* c, const void* in, void* out) {
-  return c->cfg.precision == 32 ? do_step<float>(c, in, out) : do_step<double>(c, in, out);
+hipError_t step_once(pclb_ctx* c, const void* in, void* out, void* ghost) {
+  return c->cfg.precision == 32 ? do_step<float>(c, in, out, ghost)
+                                : do_step<double>(c, in, out, ghost);
 }
+
 
 }  // namespace
 
 extern "C" {
 
 double pclb_cfl_dt(const pclb_config* cfg, double cfl) {
-  if (!cfg || !(cfg->r1 > 0) || !(cfg->r2 > cfg->r1) || cfg->n_r < 2 || cfg->n_theta < 1 || !(cfl > 0))
+  if (!cfg || !(cfg->r1 > 0) || !(cfg->r2 > cfg->r1) || cfg->n_r < 2 || cfg->n_theta < 1 ||
+      cfg->n_f < 1 || cfg->n_f > 8 || !(cfl > 0))
     return -1.0;
   double dr = (cfg->r2 - cfg->r1) / (cfg->n_r - 1);
-  double dth = 2.0 * PI / cfg->n_theta;
+  double dth = sector_dth(cfg);
   return cfl * std::fmin(dr, cfg->r1 * dth) / speed(NK);
 }
 
@@ -131,14 +136,13 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   c->cfg = *cfg;
   // launch shape of the strip kernel (results do not depend on it)
   c->tune.chunk = cfg->strip_chunk;
-  c->tune.split = cfg->strip_split;
   c->tune.order = cfg->strip_order == PCLB_ORDER_PLAIN ? 0 : 1;
-  c->tie = cfg->adjoint_tie > 0.0 ? cfg->adjoint_tie : (cfg->precision == 64 ? 1e-13 : 1e-5);
+  c->tie = cfg->adjoint_tie > 0.0 ? cfg->adjoint_tie : (cfg->precision == 64 ? 1e-13 : 1e-6);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return fail(nullptr, PCLB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
   const int nr = cfg->n_r, nth = cfg->n_theta;
   c->dr = (cfg->r2 - cfg->r1) / (nr - 1);
-  c->dth = 2.0 * PI / nth;
+  c->dth = sector_dth(cfg);
   // geometry tables: node angles theta_j = (j+1) dtheta, radii r_i = R1 + i dr
   std::string host_err;
   size_t ngeom = 2 * (size_t)nth + 2 * (size_t)nr;
@@ -162,6 +166,7 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
             hipMalloc(&c->d_diag, 8 * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->d_flag, sizeof(int)) == hipSuccess &&
             hipMalloc(&c->d_gm, 16 * (size_t)nth * sizeof(double)) == hipSuccess;
+
   if (!ok) {
     delete[] h;
     pclb_destroy(c);
@@ -169,10 +174,12 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   }
   e = hipMemcpy(c->d_geom, h, ngeom * sizeof(double), hipMemcpyHostToDevice);
   delete[] h;
+
   if (e != hipSuccess) { pclb_destroy(c); return fail(nullptr, PCLB_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e)); }
   Tables& T = c->T;
   T.nr = nr;
   T.nth = nth;
+  T.nf = cfg->n_f;
   T.dt_dr = cfg->dt / c->dr;
   T.dt_dth = cfg->dt / c->dth;
   T.e = std::exp(-cfg->dt / cfg->tau);
@@ -180,6 +187,7 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   T.sth = c->d_geom + nth;
   T.rinv = c->d_geom + 2 * nth;
   T.wA = c->d_geom + 2 * nth + nr;
+  T.n_mixed = strip_mixed_count(nth, cfg->n_f);
   for (int s = 0; s < 2; ++s) {
     c->bc.kind[s] = PCLB_WALL;
     for (int a = 0; a < 4; ++a) c->bc.p[s][a] = 0.0;
@@ -261,7 +269,7 @@ int pclb_step(pclb_ctx* c, int64_t n) {
   if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
   if (n < 0) return fail(c, PCLB_EINVAL, "negative step count");
   for (int64_t s = 0; s < n; ++s) {
-    hipError_t e = step_once(c, c->f[c->cur], c->f[1 - c->cur]);
+    hipError_t e = step_once(c, c->f[c->cur], c->f[1 - c->cur], c->d_ghost);
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
     c->cur = 1 - c->cur;
     ++c->steps;
@@ -272,7 +280,7 @@ int pclb_step(pclb_ctx* c, int64_t n) {
 int pclb_step_into(pclb_ctx* c, const void* f_in, void* f_out) {
   if (!c) return PCLB_EINVAL;
   if (!f_in || !f_out || f_in == f_out) return fail(c, PCLB_EINVAL, "distinct non-null buffers required");
-  hipError_t e = step_once(c, f_in, f_out);
+  hipError_t e = step_once(c, f_in, f_out, c->d_ghost);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   return PCLB_OK;
 }
@@ -321,6 +329,20 @@ int pclb_moments_host(pclb_ctx* c, double* diag8_host) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "diagnostics copy");
   if (diag8_host[6] != 0.0) return fail(c, PCLB_ENONFINITE, "non-finite distribution values found");
+  return PCLB_OK;
+}
+
+int pclb_noneq(pclb_ctx* c, const void* f, int32_t kinds, double* out) {
+  if (!c) return PCLB_EINVAL;
+  if (kinds <= 0 || kinds > PCLB_NONEQ_ALL) return fail(c, PCLB_EINVAL, "kinds must be a nonzero mask of PCLB_NONEQ_*");
+  if (!out) return fail(c, PCLB_EINVAL, "null output");
+  if (!f) {
+    if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
+    f = c->f[c->cur];
+  }
+  hipError_t e = c->cfg.precision == 32 ? launch_noneq<float>(c->T, f, kinds, out, c->stream)
+                                        : launch_noneq<double>(c->T, f, kinds, out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "non-equilibrium launch");
   return PCLB_OK;
 }
 

@@ -32,8 +32,7 @@ class Sim:
 
     def __init__(self, problem, precision: int = 32, kernel: int = N.KERNEL_AUTO,
                  device: str | torch.device = "cuda:0", strip_chunk: int = 0,
-                 strip_split: int = 0, strip_order: int = N.ORDER_DEFAULT,
-                 adjoint_tie: float = 0.0):
+                 strip_order: int = N.ORDER_DEFAULT, adjoint_tie: float = 0.0):
         if precision not in (32, 64):
             raise ValueError("precision must be 32 or 64")
         self.L = N.lib()
@@ -46,8 +45,9 @@ class Sim:
         self.dtype = torch.float32 if precision == 32 else torch.float64
         self.nr, self.nth = problem.nr, problem.nth
         self.cfg = N.Config(problem.nr, problem.nth, problem.r1, problem.r2, problem.tau,
-                            problem.dt, 8, 8, precision, 1, kernel, strip_chunk, strip_split,
-                            strip_order, adjoint_tie)
+                            problem.dt, 8, getattr(problem, "nf", 8), precision, 1, kernel,
+                            strip_chunk, strip_order,
+                            adjoint_tie)
         ctx = ctypes.c_void_p()
         N.check(self.L.pclb_create(ctypes.byref(self.cfg), ctypes.byref(ctx)), None)
         self.ctx = ctx
@@ -150,6 +150,17 @@ class Sim:
         out = (ctypes.c_double * 8)()
         N.check(self.L.pclb_moments_host(self.ctx, out), self.ctx)
         return np.array(out[:])
+
+    def noneq(self, kinds: int = N.NONEQ_ALL, f: torch.Tensor | None = None) -> torch.Tensor:
+        """Non-equilibrium fields (Sec. IV) of f (default: the current state):
+        tensor (n_kinds, 12, nr, nth) of the selected kinds in the order M, M*,
+        Delta, Delta*, 12 polar components each."""
+        n = bin(int(kinds) & N.NONEQ_ALL).count("1")
+        out = torch.empty((max(n, 1), 12, self.nr, self.nth), dtype=torch.float64, device=self.device)
+        if f is not None:
+            self._check_state_tensor(f)
+        N.check(self.L.pclb_noneq(self.ctx, _ptr(f), int(kinds), _ptr(out)), self.ctx)
+        return out
 
     # -- adjoint -----------------------------------------------------------
     def adjoint_step(self, f_t: torch.Tensor, lam_next: torch.Tensor, lam_out: torch.Tensor):

@@ -59,6 +59,7 @@ class Problem:
     bc_kind: tuple = (WALL, WALL)
     bc_par: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
     params: dict = field(default_factory=dict, compare=False, hash=False)
+    nf: int = 8          # theta covers 0 < theta <= 2 pi nf / 8 (8: the full annulus)
 
     @property
     def dr(self) -> float:
@@ -66,25 +67,25 @@ class Problem:
 
     @property
     def dth(self) -> float:
-        return 2.0 * math.pi / self.nth
+        return 2.0 * math.pi * self.nf / (8.0 * self.nth)
 
     @property
     def nodes(self) -> int:
         return self.nr * self.nth
 
 
-def cfl_dt(nr: int, nth: int, r1: float, r2: float, cfl: float = 0.3) -> float:
+def cfl_dt(nr: int, nth: int, r1: float, r2: float, cfl: float = 0.3, nf: int = 8) -> float:
     """dt = cfl * min(dr, R1 dtheta) / max|v| (the configs' time-step rule)."""
     dr = (r2 - r1) / (nr - 1)
-    dth = 2.0 * math.pi / nth
+    dth = 2.0 * math.pi * nf / (8.0 * nth)
     return cfl * min(dr, r1 * dth) / MAX_SPEED
 
 
-def node_coords(nr: int, nth: int, r1: float, r2: float):
-    """r_i = R1 + i dr, theta_j = (j+1) dtheta (Sec. II.C node placement,
-    0-based); returns 2-D arrays R[i, j], TH[i, j]."""
+def node_coords(nr: int, nth: int, r1: float, r2: float, nf: int = 8):
+    """r_i = R1 + i dr, theta_j = (j+1) dtheta with dtheta = 2 pi nf / (8 nth)
+    (Sec. II.C node placement, 0-based); returns 2-D arrays R[i, j], TH[i, j]."""
     dr = (r2 - r1) / (nr - 1)
-    dth = 2.0 * math.pi / nth
+    dth = 2.0 * math.pi * nf / (8.0 * nth)
     r = r1 + dr * np.arange(nr, dtype=np.float64)
     th = dth * (np.arange(nth, dtype=np.float64) + 1.0)
     return np.meshgrid(r, th, indexing="ij")
@@ -196,6 +197,28 @@ def kelvin_helmholtz(nr=4096, nth=8192, steps=1000, tau=1e-5, warmup=50, cfl=Non
     return P, dict(rho=np.ones_like(R), ur=ur, ut=ut, T=np.ones_like(R))
 
 
+def couette(nr=100, nth=20, steps=4000, tau=0.2, omega=(-0.1, 0.1), nf=1, dt=1e-3):
+    """Flow between coaxial cylinders R1 = 1 and R2 = 2 turning at omega[0]
+    and omega[1], started at rest with rho = T = 1, on the sector
+    0 < theta <= 2 pi nf / 8 (Sec. III.A: 100 x 20 nodes, one eighth of the
+    annulus, dt = 1e-3, tau from 0.2 down to 0.01).  The steady state tends to
+    u_theta = A r + B / r (Eq. RSF)."""
+    r1, r2 = 1.0, 2.0
+    P = Problem("couette", nr, nth, r1, r2, tau, dt, steps, (WALL, WALL),
+                ((omega[0], 0, 0, 0), (omega[1], 0, 0, 0)), {"omega": tuple(omega)}, nf)
+    R, _ = node_coords(nr, nth, r1, r2, nf)
+    z = np.zeros_like(R)
+    return P, dict(rho=np.ones_like(R), ur=z, ut=z.copy(), T=np.ones_like(R))
+
+
+def couette_profile(r, r1=1.0, r2=2.0, omega=(-0.1, 0.1)):
+    """Eq. RSF: u_theta = A r + B / r with A, B from u = R omega at both walls."""
+    w1, w2 = omega
+    A = (w2 * r2 ** 2 - w1 * r1 ** 2) / (r2 ** 2 - r1 ** 2)
+    B = r1 ** 2 * r2 ** 2 * (w1 - w2) / (r2 ** 2 - r1 ** 2)
+    return A * np.asarray(r) + B / np.asarray(r)
+
+
 def uniform(nr, nth, r1=1.0, r2=2.0, rho=1.0, ux=0.0, uy=0.0, T=1.0, tau=1e-3,
             bc=(WALL, WALL), bc_par=((0, 0, 0, 0), (0, 0, 0, 0)), cfl=0.3):
     """A uniform state with Cartesian velocity (ux, uy), given in polar
@@ -209,21 +232,23 @@ def uniform(nr, nth, r1=1.0, r2=2.0, rho=1.0, ux=0.0, uy=0.0, T=1.0, tau=1e-3,
 
 
 def smooth_random(nr, nth, r1=1.0, r2=2.0, tau=2e-3, seed=0, amp=0.05, cfl=0.3,
-                  bc=(WALL, WALL), bc_par=((0.1, 0, 0, 0), (-0.05, 0, 0, 0))):
+                  bc=(WALL, WALL), bc_par=((0.1, 0, 0, 0), (-0.05, 0, 0, 0)), nf=8):
     """Smooth seeded fields: a few low azimuthal/radial modes around rho = 1,
-    T = 1, u = 0, with relative amplitude ``amp``."""
+    T = 1, u = 0, with relative amplitude ``amp``; on a sector (nf < 8) the
+    azimuthal modes are periodic over the sector."""
     rng = np.random.default_rng(seed)
-    dt = cfl_dt(nr, nth, r1, r2, cfl)
-    P = Problem("smooth_random", nr, nth, r1, r2, tau, dt, 0, bc, bc_par, {"seed": seed})
-    R, TH = node_coords(nr, nth, r1, r2)
+    dt = cfl_dt(nr, nth, r1, r2, cfl, nf)
+    P = Problem("smooth_random", nr, nth, r1, r2, tau, dt, 0, bc, bc_par, {"seed": seed}, nf)
+    R, TH = node_coords(nr, nth, r1, r2, nf)
     x = (R - r1) / (r2 - r1)
+    period = 8.0 / nf
 
     def modes(scale):
         out = np.zeros_like(R)
         for m in range(1, 4):
             for n in range(1, 3):
                 a, b, ph = rng.uniform(-1, 1, 3)
-                out += scale * a * np.cos(m * TH + math.pi * ph) * np.sin(math.pi * n * x + b)
+                out += scale * a * np.cos(m * period * TH + math.pi * ph) * np.sin(math.pi * n * x + b)
         return out
 
     rho = 1.0 + modes(amp)

@@ -31,8 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 def cfg(**kw):
     base = dict(n_r=64, n_theta=128, r1=1.0, r2=2.0, tau=1e-4, dt=1e-3, n_i=8, n_f=8,
-                precision=64, fp64_collision=1, kernel=0, strip_chunk=0, strip_split=0,
-                strip_order=0, adjoint_tie=0.0)
+                precision=64, fp64_collision=1, kernel=0, strip_chunk=0, strip_order=0,
+                adjoint_tie=0.0)
     base.update(kw)
     return N.Config(*[base[k] for k, _ in N.Config._fields_])
 
@@ -42,11 +42,16 @@ def test_cfl_dt_matches_workload_rule():
     dt = N.lib().pclb_cfl_dt(ctypes.byref(c), 0.3)
     assert abs(dt - W.cfl_dt(64, 128, 1.0, 2.0, 0.3)) < 1e-18
     assert N.lib().pclb_cfl_dt(ctypes.byref(cfg(r1=-1.0)), 0.3) < 0
+    # a sector of one eighth: dtheta is 8 times smaller
+    dt1 = N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_f=1, n_theta=20)), 0.3)
+    assert abs(dt1 - W.cfl_dt(64, 20, 1.0, 2.0, 0.3, nf=1)) < 1e-18
+    assert N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_f=0)), 0.3) < 0
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(r1=0.0), -1), (dict(r2=0.5), -1), (dict(n_r=3), -1), (dict(n_theta=4), -1),
-    (dict(tau=0.0), -1), (dict(dt=-1.0), -1), (dict(n_i=16), -1), (dict(n_f=1), -1),
+    (dict(tau=0.0), -1), (dict(dt=-1.0), -1), (dict(n_i=16), -1), (dict(n_f=0), -1),
+    (dict(n_f=9), -1), (dict(n_f=1, dt=2e-3), -2),
     (dict(precision=16), -1), (dict(kernel=7), -1), (dict(dt=0.01), -2),
     (dict(fp64_collision=0), -1), (dict(adjoint_tie=-1.0), -1), (dict(adjoint_tie=0.5), -1),
 ])
@@ -60,11 +65,10 @@ def test_create_rejects_invalid_config(kw, code):
 
 
 @pytest.mark.parametrize("field,val", [("strip_chunk", 65), ("strip_chunk", -1),
-                                       ("strip_split", 3), ("strip_split", 8),
-                                       ("strip_order", 3)])
+                                       ("strip_order", 3), ("strip_order", -1)])
 def test_create_rejects_strip_shape_out_of_range(field, val):
     """The strip kernel holds 1/r of a chunk one row per lane: more than 64
-    rows per chunk (or an unknown split or order) is refused at creation,
+    rows per chunk (or an unknown workgroup order) is refused at creation,
     before any device call."""
     L = N.lib()
     ctx = ctypes.c_void_p()

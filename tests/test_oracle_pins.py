@@ -19,7 +19,7 @@ RNG = np.random.default_rng(12345)
 
 
 def grid_of(P, terms=7):
-    return O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par, terms)
+    return O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par, terms, P.nf)
 
 
 # --------------------------------------------------------------------------
