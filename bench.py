@@ -83,6 +83,72 @@ def run_forward(W, Sim, torch, precision, steps, warmup, nr=4096, nth=8192):
     return P, ms, d
 
 
+def run_variants(W, Sim, torch, steps=20, warmup=3):
+    """FP32 step time on the headline workload for each convection scheme and
+    relaxation form (the comparison schemes run on the node kernel, MWB on
+    the strip kernel and, for reference, on the node kernel), and the time of
+    the non-equilibrium fields kernel (all four kinds) on the same state."""
+    import ctypes
+    from paper_1302_7104_amd import _native as N
+    P, F = W.kelvin_helmholtz(4096, 8192, steps)
+    nodes = P.nr * P.nth
+    step_bytes = 2 * NQ * nodes * 4
+    out = {}
+    variants = (("mwb_strip", {}), ("mwb_node", {"kernel": N.KERNEL_NODE}),
+                ("mwb_euler_relaxation_strip", {"relaxation": N.RELAX_EULER}),
+                ("warming_beam_node", {"scheme": N.SCHEME_WB}),
+                ("lax_wendroff_node", {"scheme": N.SCHEME_LW}),
+                ("upwind2_node", {"scheme": N.SCHEME_UPWIND2}))
+    for name, kw in variants:
+        sim = Sim(P, precision=32, **kw)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        sim.step(warmup)
+        ms = time_steps(sim, torch, steps)
+        out[name] = {"ms_per_step": ms, "hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if name == "mwb_strip":
+            # Sec. IV fields: read the state (132 B per node), write 4 kinds x 12
+            # components in double (384 B per node)
+            res = torch.empty((4, 12, P.nr, P.nth), dtype=torch.float64, device=sim.device)
+            ptr = ctypes.c_void_p(res.data_ptr())
+            N.check(sim.L.pclb_noneq(sim.ctx, None, N.NONEQ_ALL, ptr), sim.ctx)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(sim.stream)
+            for _ in range(5):
+                N.check(sim.L.pclb_noneq(sim.ctx, None, N.NONEQ_ALL, ptr), sim.ctx)
+            e1.record(sim.stream)
+            torch.cuda.synchronize()
+            ms_nq = e0.elapsed_time(e1) / 5
+            nq_bytes = nodes * (NQ * 4 + 4 * 12 * 8)
+            out["noneq_all_kinds"] = {"ms": ms_nq, "bytes_per_node": NQ * 4 + 4 * 12 * 8,
+                                      "achieved_gbs": nq_bytes / (ms_nq * 1e-3) / 1e9,
+                                      "hbm_frac": nq_bytes / (ms_nq * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del res
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
+def couette_errors(W, Sim, torch):
+    """Sec. III.A: the one-eighth-sector rotating-cylinder run (100 x 20) from
+    rest to steady state in FP64 for each relaxation time; the largest
+    departure of the theta-mean u_theta from Eq. RSF, relative to R2 omega2."""
+    import numpy as np
+    out = {}
+    for tau, t_end in ((0.2, 10.0), (0.1, 15.0), (0.05, 20.0), (0.01, 40.0)):
+        P, F = W.couette(tau=tau, steps=int(round(t_end / 1e-3)))
+        sim = Sim(P, precision=64)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        sim.step(P.steps)
+        u = sim.fields()["ut"].mean(1).cpu().numpy()
+        sim.close()
+        R, _ = W.node_coords(P.nr, P.nth, P.r1, P.r2, P.nf)
+        out[f"tau_{tau:g}"] = float(np.abs(u - W.couette_profile(R[:, 0])).max() / 0.2)
+    return out
+
+
 def adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, precision):
     """J = sum over 1.1 < r < 1.5 of rho^2 r dr dtheta after `steps` steps of
     the Richtmyer-Meshkov recipe, and dJ/da_k through the hand-written
@@ -398,6 +464,9 @@ def main():
                          "Richtmyer-Meshkov) and exit")
     ap.add_argument("--accuracy-only", action="store_true",
                     help="FP32 error against FP64 after the full run of every configuration")
+    ap.add_argument("--variants-only", action="store_true",
+                    help="step time per convection scheme, the non-equilibrium fields kernel and "
+                         "the Couette errors, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -436,6 +505,11 @@ def main():
         for name in ACCURACY_RUNS:
             print(json.dumps({name: fp32_accuracy(W, torch, name)}), flush=True)
         return
+    if args.variants_only:
+        print(json.dumps({"schemes_and_noneq_kh4096x8192_fp32": run_variants(W, Sim, torch)}),
+              flush=True)
+        print(json.dumps({"couette_sector_steady_error": couette_errors(W, Sim, torch)}), flush=True)
+        return
     P, ms, diag = run_forward(W, Sim, torch, 32, args.steps, args.warmup)
     if args.calibrate_copy:
         calibrate_copy(torch)
@@ -473,6 +547,8 @@ def main():
         extra["adjoint_rm_1024x2048"] = run_adjoint(W, torch)
         extra["fp32_error_vs_fp64_after_run"] = {name: fp32_accuracy(W, torch, name)
                                                  for name in ACCURACY_RUNS}
+        extra["schemes_and_noneq_kh4096x8192_fp32"] = run_variants(W, Sim, torch)
+        extra["couette_sector_steady_error"] = couette_errors(W, Sim, torch)
     out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)

@@ -74,6 +74,22 @@ enum {
   PCLB_KERNEL_STRIP = 2    /* r-marching 64-column theta strips with a register ring */
 };
 
+/* Convection scheme (pclb_config.scheme): the paper's MWB scheme and the three
+ * it is compared with (Sec. II.B; Sec. III.A, Figs. 5 and 6).  Only MWB runs on
+ * the strip kernel and has an adjoint. */
+enum {
+  PCLB_SCHEME_MWB = 0,     /* Eq. MWB Scheme with S(eta) = (|eta| - 1) / (|eta| + 1) */
+  PCLB_SCHEME_WB = 1,      /* Warming-Beam, Eq. WB_Scheme_1 */
+  PCLB_SCHEME_LW = 2,      /* Lax-Wendroff: Eq. Taylor expansion with central differences */
+  PCLB_SCHEME_UPWIND2 = 3  /* second-order upwind, Eq. upwind scheme_1, Euler in time */
+};
+
+/* Relaxation over a step (pclb_config.relaxation), Sec. II.B. */
+enum {
+  PCLB_RELAX_ANALYTIC = 0, /* Eq. operator1_new: f^eq + (f - f^eq) exp(-dt/tau) */
+  PCLB_RELAX_EULER = 1     /* Eq. operator1_old: f - dt/tau (f - f^eq) */
+};
+
 /* Workgroup order of the strip kernel (pclb_config.strip_order). */
 enum {
   PCLB_ORDER_DEFAULT = 0,
@@ -109,6 +125,8 @@ typedef struct pclb_config {
                             counts as zero in pclb_adjoint_step; 0 selects the
                             default of the precision (1e-13 for 64, 1e-6 for
                             32); must be >= 0 and < 1e-2 */
+  int32_t scheme;        /* PCLB_SCHEME_*; 0 is the paper's combined scheme */
+  int32_t relaxation;    /* PCLB_RELAX_* */
 } pclb_config;
 
 /* Courant-number time step: dt = cfl * min(dr, r1*dtheta) / 4.49, 4.49 being
@@ -118,8 +136,9 @@ double pclb_cfl_dt(const pclb_config* cfg, double cfl);
 
 /* Validate cfg and create a context on the current HIP device.  Checks
  * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i = 8, n_f in 1..8,
- * precision in {32, 64}, fp64_collision = 1, the launch-shape fields and
- * adjoint_tie in range (PCLB_EINVAL), and max |C_r|, |C_theta| <= 1 (the
+ * precision in {32, 64}, fp64_collision = 1, the launch-shape fields,
+ * adjoint_tie, scheme and relaxation in range (PCLB_EINVAL), and
+ * max |C_r|, |C_theta| <= 1 (the
  * monotone range of Sec. II.B, Eqs. varphi_0-varphi2e) -> PCLB_ECFL.  Allocates the
  * context's small device tables and scratch (ghost layers, reduction
  * partials).  *out is owned by the caller until pclb_destroy.  Both radial

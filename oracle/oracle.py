@@ -24,6 +24,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 NQ = 33
 WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
+# convection schemes and relaxation forms (Sec. II.B; Sec. III.A, Figs. 5-6)
+SCHEME_MWB, SCHEME_WB, SCHEME_LW, SCHEME_UPWIND2 = 0, 1, 2, 3
+RELAX_ANALYTIC, RELAX_EULER = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -44,7 +47,8 @@ class _OrGrid(ctypes.Structure):
                 ("tau", ctypes.c_double), ("dt", ctypes.c_double),
                 ("bc_kind", ctypes.c_int32 * 2),
                 ("bc_par", (ctypes.c_double * 4) * 2),
-                ("terms", ctypes.c_int32), ("nf", ctypes.c_int32)]
+                ("terms", ctypes.c_int32), ("nf", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("relax", ctypes.c_int32)]
 
 
 @dataclass
@@ -61,6 +65,8 @@ class Grid:
     bc_par: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
     terms: int = 7
     nf: int = 8           # theta covers 2 pi nf / 8 (Sec. II.C); 8 = full annulus
+    scheme: int = 0       # SCHEME_MWB, SCHEME_WB, SCHEME_LW, SCHEME_UPWIND2
+    relax: int = 0        # RELAX_ANALYTIC (Eq. operator1_new), RELAX_EULER (Eq. operator1_old)
 
     def c(self) -> _OrGrid:
         if not 1 <= int(self.nf) <= 8:
@@ -75,6 +81,8 @@ class Grid:
                 g.bc_par[s][a] = float(p[a])
         g.terms = self.terms
         g.nf = int(self.nf)
+        g.scheme = int(self.scheme)
+        g.relax = int(self.relax)
         return g
 
 
@@ -97,6 +105,8 @@ def lib():
         L.or_mwb_term.argtypes = [ctypes.c_double, _D, ctypes.c_int32]
         L.or_mwb_term.restype = ctypes.c_double
         L.or_mwb_term_eta.argtypes = [ctypes.c_double, _D]
+        L.or_convection_term.argtypes = [ctypes.c_int32, ctypes.c_double, _D]
+        L.or_convection_term.restype = ctypes.c_double
         L.or_mwb_term_eta.restype = ctypes.c_double
         L.or_mwb_grad.argtypes = [ctypes.c_double, _D, ctypes.c_double, _D]
         L.or_step.argtypes = [G, _D, _D, ctypes.c_int32]
@@ -106,6 +116,7 @@ def lib():
         L.or_fields.argtypes = [G, _D, _D, _D, _D, _D]
         L.or_diagnostics.argtypes = [G, _D, _D]
         L.or_adjoint_step.argtypes = [G, _D, _D, ctypes.c_double, _D]
+        L.or_adjoint_step.restype = ctypes.c_int
         L.or_adjoint_init.argtypes = [G, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.or_noneq.argtypes = [G, _D, _D]
         L.or_noneq_sample.argtypes = [G, _D, _I, ctypes.c_int32, _D]
@@ -161,6 +172,13 @@ def relax_node(f33, dt, tau) -> np.ndarray:
 
 #: tie threshold of the adjoint for states computed in double precision
 TIE_FP64 = 1e-13
+
+
+def convection_term(scheme: int, C, psi5) -> float:
+    """psi_j^n - psi_j^{n+1} of one sweep of the given scheme (SCHEME_*) for
+    psi_{j-2..j+2} at Courant number C."""
+    psi5 = _f64(psi5)
+    return lib().or_convection_term(int(scheme), float(C), _p(psi5))
 
 
 def mwb_term(C, psi5, s_mode: int = 0) -> float:
@@ -239,7 +257,8 @@ def adjoint_step(grid: Grid, f_t: np.ndarray, lam_next: np.ndarray,
     f_t = _f64(f_t); lam_next = _f64(lam_next)
     out = np.empty_like(f_t)
     g = grid.c()
-    lib().or_adjoint_step(ctypes.byref(g), _p(f_t), _p(lam_next), float(tie_eps), _p(out))
+    if lib().or_adjoint_step(ctypes.byref(g), _p(f_t), _p(lam_next), float(tie_eps), _p(out)):
+        raise ValueError("the oracle's adjoint covers the combined MWB step only")
     return out
 
 

@@ -225,6 +225,31 @@ double mwb_term_eta(double C, const double psi[5]) {
   return (C + 0.5 * C * (1.0 - std::fabs(C)) * (1.0 - S) * (1.0 - eta)) * delta;
 }
 
+// The convection term T = psi_j^n - psi_j^{n+1} of one sweep for each scheme
+// the paper compares (Sec. II.B; Sec. III.A, Figs. 5 and 6), psi holding
+// psi_{j-2..j+2}:
+//  0 MWB: Eq. MWB Scheme (mwb_term);
+//  1 Warming-Beam, Eq. WB_Scheme_1 as printed;
+//  2 Lax-Wendroff: Eq. Taylor expansion with both derivatives taken by
+//    central differences (the paper names the scheme without printing it);
+//  3 second-order upwind: Eq. Taylor expansion cut after the first-order
+//    term, the derivative from Eq. upwind scheme_1 (forward Euler in time).
+double convection_term(int scheme, double C, const double psi[5]) {
+  const double pm2 = psi[0], pm1 = psi[1], p0 = psi[2], pp1 = psi[3], pp2 = psi[4];
+  switch (scheme) {
+    case 1:
+      if (C >= 0) return C * (p0 - pm1) + 0.5 * C * (1.0 - C) * (p0 - 2.0 * pm1 + pm2);
+      return C * (pp1 - p0) - 0.5 * C * (1.0 + C) * (p0 - 2.0 * pp1 + pp2);
+    case 2:
+      return 0.5 * C * (pp1 - pm1) - 0.5 * C * C * (pp1 - 2.0 * p0 + pm1);
+    case 3:
+      if (C >= 0) return C * (3.0 * p0 - 4.0 * pm1 + pm2) / 2.0;
+      return -C * (3.0 * p0 - 4.0 * pp1 + pp2) / 2.0;
+    default:
+      return mwb_term<double>(C, psi, 0);
+  }
+}
+
 // Partial derivatives of mwb_term with respect to psi_{j-2..j+2}, written as
 // derivatives of the term in (delta, delta') mapped back to the stencil.
 //
@@ -289,6 +314,9 @@ struct OrGrid {
   double bc_par[2][4];
   int32_t terms;
   int32_t nf;   // N_f: theta covers 0 < theta <= 2 pi N_f / N_i (N_i = 8; 8 = full annulus)
+  int32_t scheme;  // convection: 0 MWB (Eq. MWB Scheme), 1 Warming-Beam (Eq. WB_Scheme_1),
+                   // 2 Lax-Wendroff, 3 second-order upwind (Sec. II.B, Sec. III.A Figs. 5-6)
+  int32_t relax;   // relaxation: 0 analytic (Eq. operator1_new), 1 forward Euler (Eq. operator1_old)
 };
 
 namespace {
@@ -323,6 +351,13 @@ struct Padded {
 
 inline size_t idx(const OrGrid& g, int q, int i, int j) {
   return ((size_t)q * g.nr + i) * g.nth + j;
+}
+
+// The relaxation of one value over a step (Sec. II.B): Eq. operator1_new
+// (relax = 0) or Eq. operator1_old (relax = 1).
+double relax_value(const OrGrid& g, double f, double feq) {
+  if (g.relax == 1) return f - g.dt / g.tau * (f - feq);
+  return feq + (f - feq) * std::exp(-g.dt / g.tau);
 }
 
 // mod{a, b} of Sec. II.B: a for a <= b, a - b above (a in 1..2b).
@@ -488,6 +523,10 @@ double or_mwb_term(double C, const double* psi, int32_t s_mode) {
 
 double or_mwb_term_eta(double C, const double* psi) { return mwb_term_eta(C, psi); }
 
+double or_convection_term(int32_t scheme, double C, const double* psi) {
+  return convection_term(scheme, C, psi);
+}
+
 void or_mwb_grad(double C, const double* psi, double tie_eps, double* g) {
   mwb_grad(C, psi, tie_eps, g);
 }
@@ -502,7 +541,6 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
   size_t tot = (size_t)NQ * g.nr * g.nth;
   std::vector<double> cur(f_in, f_in + tot), m;
   Padded P(g.nr, g.nth);
-  double e = std::exp(-g.dt / g.tau);
   int bad = 0;
   for (int s = 0; s < nsteps; ++s) {
     all_macros(g, cur.data(), m);                 // moments of every real node
@@ -518,17 +556,17 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
         for (int q = 0; q < NQ; ++q) {
           double ft = P.at(q, i, j);
           double out = 0.0;
-          if (g.terms & 1) out += fe[q] + (ft - fe[q]) * e;   // Eq. operator1_new
+          if (g.terms & 1) out += relax_value(g, ft, fe[q]);   // Eqs. operator1_new / _old
           else out += ft;
           double Cr = vr_of(q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
           double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
           if (g.terms & 2) {
             double psi[5] = {P.at(q, i - 2, j), P.at(q, i - 1, j), ft, P.at(q, i + 1, j), P.at(q, i + 2, j)};
-            out -= mwb_term<double>(Cr, psi, 0);
+            out -= convection_term(g.scheme, Cr, psi);
           }
           if (g.terms & 4) {
             double psi[5] = {P.at(q, i, j - 2), P.at(q, i, j - 1), ft, P.at(q, i, j + 1), P.at(q, i, j + 2)};
-            out -= mwb_term<double>(Ct, psi, 0);
+            out -= convection_term(g.scheme, Ct, psi);
           }
           f_out[idx(g, q, i, j)] = out;
         }
@@ -552,7 +590,6 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
                     double* out) {
   const OrGrid& g = *gp;
   Geometry geo(g);
-  double e = std::exp(-g.dt / g.tau);
 #pragma omp parallel for schedule(dynamic)
   for (int n = 0; n < count; ++n) {
     const int i = nodes[2 * n], j = nodes[2 * n + 1];
@@ -593,7 +630,7 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
     double r = geo.rr(i);
     for (int q = 0; q < NQ; ++q) {
       double ft = f[idx(g, q, i, j)];
-      double res = fe[q] + (ft - fe[q]) * e;
+      double res = relax_value(g, ft, fe[q]);
       double Cr = vr_of(q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
       double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
       double pr[5], pt[5];
@@ -601,8 +638,8 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
         pr[s] = value(q, i - 2 + s, j);
         pt[s] = value(q, i, j - 2 + s);
       }
-      res -= mwb_term<double>(Cr, pr, 0);
-      res -= mwb_term<double>(Ct, pt, 0);
+      res -= convection_term(g.scheme, Cr, pr);
+      res -= convection_term(g.scheme, Ct, pt);
       out[(size_t)n * NQ + q] = res;
     }
   }
@@ -682,16 +719,19 @@ void or_diagnostics(const OrGrid* gp, const double* f, double* out) {
 // it depends on.  tie_eps is the relative size below which an upwind
 // difference counts as zero (the derivative convention of mwb_grad): 1e-13
 // suits a state computed in double precision.
-void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next, double tie_eps,
-                     double* lam_out) {
+int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next, double tie_eps,
+                    double* lam_out) {
   const OrGrid& g = *gp;
+  if (g.scheme != 0 || g.terms != 7) return -1;   // the adjoint of the combined MWB step only
   Geometry geo(g);
   size_t tot = (size_t)NQ * g.nr * g.nth, n = (size_t)g.nr * g.nth;
   std::vector<double> m;
   all_macros(g, f_t, m);
   Padded P(g.nr, g.nth);
   build_padded(g, geo, f_t, m, P);
-  double e = std::exp(-g.dt / g.tau);
+  // d(relaxed f)/df = e + (1 - e) df^eq/df for both relaxations: Eq.
+  // operator1_new has e = exp(-dt/tau), Eq. operator1_old e = 1 - dt/tau
+  double e = g.relax == 1 ? 1.0 - g.dt / g.tau : std::exp(-g.dt / g.tau);
 
   // adjoint of the four linear moments of every real node
   std::vector<double> gM((size_t)4 * n, 0.0);
@@ -811,6 +851,7 @@ void or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next
                                     gM[3 * n + c] * ph3;
       }
     }
+  return 0;
 }
 
 // Adjoint of or_init_feq: given lam = dJ/df at the initial state, return

@@ -21,6 +21,8 @@ WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
 KERNEL_AUTO, KERNEL_NODE, KERNEL_STRIP = 0, 1, 2
 ORDER_DEFAULT, ORDER_XCD, ORDER_PLAIN = 0, 1, 2
 NONEQ_M, NONEQ_MSTAR, NONEQ_DELTA, NONEQ_DSTAR, NONEQ_ALL = 1, 2, 4, 8, 15
+SCHEME_MWB, SCHEME_WB, SCHEME_LW, SCHEME_UPWIND2 = 0, 1, 2, 3
+RELAX_ANALYTIC, RELAX_EULER = 0, 1
 
 #: every symbol include/pclb.h declares
 SYMBOLS = (
@@ -45,7 +47,8 @@ class Config(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("fp64_collision", ctypes.c_int32),
                 ("kernel", ctypes.c_int32),
                 ("strip_chunk", ctypes.c_int32), ("strip_order", ctypes.c_int32),
-                ("adjoint_tie", ctypes.c_double)]
+                ("adjoint_tie", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("relaxation", ctypes.c_int32)]
 
 
 _lib = None

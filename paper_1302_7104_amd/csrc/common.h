@@ -93,7 +93,11 @@ struct Tables {
   const double* rinv;  // 1 / r_i, i = 0..nr-1
   const double* wA;    // quadrature weight r_i w_i dr dtheta of row i
   int32_t n_mixed;     // strips of the strip kernel that contain an octant boundary
+  int32_t scheme;      // convection scheme (SCH_* below)
 };
+
+// Convection schemes (Sec. II.B; the comparison of Sec. III.A, Figs. 5-6).
+constexpr int SCH_MWB = 0, SCH_WB = 1, SCH_LW = 2, SCH_UPWIND2 = 3;
 
 // Radial boundary description as the kernels see it.
 struct BCdev {
@@ -377,6 +381,23 @@ PCLB_HD inline R mwb_update_d(double rel, R aCr, R Kr, R d1r, R d2r, R aCt, R Kt
   return (R)((rel - (double)tr) - (double)tt);
 }
 
+// The convection term of each scheme in the same upwind form: with
+// |C| = aC, K = |C|(1 - |C|), d1 = c - u1, d2 = u1 - u2 and the downwind
+// difference dw = w1 - c (w1 one node downwind),
+//   MWB:                 aC d1 + K (d1 - d2) |d1| / (|d1| + |d2|)
+//   Warming-Beam:        aC d1 + K/2 (d1 - d2)       (the MWB bracket with S = 0)
+//   Lax-Wendroff:        aC d1 + K/2 (dw - d1)
+//   second-order upwind: aC d1 + aC/2 (d1 - d2)
+// (each equals the scheme's printed or textbook form for either sign of C).
+template <int SCH, class R>
+PCLB_HD inline R conv_term(R aC, R K, R c, R u1, R u2, R w1) {
+  const R d1 = c - u1, d2 = u1 - u2;
+  if constexpr (SCH == SCH_WB) return aC * d1 + (R)0.5 * K * (d1 - d2);
+  else if constexpr (SCH == SCH_LW) return aC * d1 + (R)0.5 * K * ((w1 - c) - d1);
+  else if constexpr (SCH == SCH_UPWIND2) return aC * d1 + (R)0.5 * aC * (d1 - d2);
+  else return aC * d1 + K * mwb_lim<R>(d1, d2);
+}
+
 // The same from the centre value c and the upwind neighbours.
 template <class R>
 PCLB_HD inline R mwb_update(double rel, R c, R aCr, R Kr, R u1r, R u2r, R aCt, R Kt, R u1t, R u2t) {
@@ -398,7 +419,7 @@ PCLB_HD inline void for_k(Fn&& fn) {
 // included) and azimuthal neighbours col(q, dj) at columns j+dj of row i.
 // put(q, value) receives f_q at t + dt as soon as it is computed (so that a
 // kernel can store it at once instead of holding all 33 results).
-template <class R, class RowFn, class ColFn, class PutFn>
+template <class R, int SCH = SCH_MWB, class RowFn, class ColFn, class PutFn>
 PCLB_HD inline void node_update_put(const Tables& T, int i, int j, const R* fc, RowFn row,
                                     ColFn col, PutFn put) {
   const double ct = T.cth[j], st = T.sth[j];
@@ -433,18 +454,27 @@ PCLB_HD inline void node_update_put(const Tables& T, int i, int j, const R* fc, 
         const int q = qidx(k, d);
         const int sr = ((G.rback >> d) & 1u) ? -1 : 1;   // upwind offset in r
         const int sc = ((G.tback >> d) & 1u) ? -1 : 1;   // upwind offset in theta
-        put(q, mwb_update<R>(rel[h], fc[q], aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt,
-                             col(q, sc), col(q, 2 * sc)));
+        if constexpr (SCH == SCH_MWB) {
+          put(q, mwb_update<R>(rel[h], fc[q], aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt,
+                               col(q, sc), col(q, 2 * sc)));
+        } else {
+          // the downwind neighbours only matter to Lax-Wendroff
+          const R wr = SCH == SCH_LW ? row(q, -sr) : fc[q];
+          const R wt = SCH == SCH_LW ? col(q, -sc) : fc[q];
+          const R tr = conv_term<SCH, R>(aCr, Kr, fc[q], row(q, sr), row(q, 2 * sr), wr);
+          const R tt = conv_term<SCH, R>(aCt, Kt, fc[q], col(q, sc), col(q, 2 * sc), wt);
+          put(q, (R)((rel[h] - (double)tr) - (double)tt));
+        }
       }
     }
   });
 }
 
 // The same with the results in res[0..NQ-1].
-template <class R, class RowFn, class ColFn>
+template <class R, int SCH = SCH_MWB, class RowFn, class ColFn>
 PCLB_HD inline void node_update(const Tables& T, int i, int j, const R* fc, RowFn row, ColFn col,
                                 R* res) {
-  node_update_put<R>(T, i, j, fc, row, col, [&](int q, R v) { res[q] = v; });
+  node_update_put<R, SCH>(T, i, j, fc, row, col, [&](int q, R v) { res[q] = v; });
 }
 
 // Ghost layers of one wall and column (Sec. II.C, radial boundary condition):

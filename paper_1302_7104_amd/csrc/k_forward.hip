@@ -46,7 +46,7 @@ __device__ inline R fetch(const R* __restrict__ f, const R* __restrict__ ghost, 
   return f[q * plane + (size_t)i * nth + j];
 }
 
-template <class R>
+template <class R, int SCH, bool SECTOR>
 __device__ inline void node_step_at(const Tables& T, const R* __restrict__ f, R* __restrict__ out,
                                     const R* __restrict__ ghost, int i, int j) {
   const int nr = T.nr, nth = T.nth;
@@ -57,34 +57,49 @@ __device__ inline void node_step_at(const Tables& T, const R* __restrict__ f, R*
   for (int q = 0; q < NQ; ++q) fc[q] = f[q * plane + c0];
   auto row = [&](int q, int di) { return fetch(f, ghost, q, i + di, j, nr, nth, plane); };
   // theta neighbours; across the ends of a sector the direction index rotates
-  const int s_lo = T.nf & 7, s_hi = (8 - T.nf) & 7;
   auto col = [&](int q, int dj) {
     int t = j + dj, qq = q;
-    if (t < 0) {
-      t += nth;
-      qq = rot_q(q, s_lo);
-    } else if (t >= nth) {
-      t -= nth;
-      qq = rot_q(q, s_hi);
+    if constexpr (SECTOR) {
+      const int s_lo = T.nf & 7, s_hi = (8 - T.nf) & 7;
+      if (t < 0) {
+        t += nth;
+        qq = rot_q(q, s_lo);
+      } else if (t >= nth) {
+        t -= nth;
+        qq = rot_q(q, s_hi);
+      }
+    } else {
+      t = t < 0 ? t + nth : (t >= nth ? t - nth : t);
     }
     return f[qq * plane + (size_t)i * nth + t];
   };
   // each result is stored as soon as it is computed: holding all 33 (with the
   // centre values and the neighbours in flight) kept the kernel at one wave
   // per SIMD
-  node_update_put<R>(T, i, j, fc, row, col, [&](int q, R v) { out[q * plane + c0] = v; });
+  node_update_put<R, SCH>(T, i, j, fc, row, col, [&](int q, R v) { out[q * plane + c0] = v; });
 }
 
 // Three waves per SIMD: the FP64 kernel then keeps 168 VGPRs and spills 24
 // of them to scratch, which is still faster than two waves without spills
 // (6.3 against 6.8 ms per step at 4096 x 8192; four waves: 8.9 ms).
-template <class R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
+#ifndef PCLB_NODE_WAVES
+#define PCLB_NODE_WAVES 3
+#endif
+template <class R, int SCH, bool SECTOR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PCLB_NODE_WAVES, PCLB_NODE_WAVES)))
 step_node_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
                  const R* __restrict__ ghost) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= T.nth) return;
-  node_step_at<R>(T, f, out, ghost, blockIdx.y, j);
+  node_step_at<R, SCH, SECTOR>(T, f, out, ghost, blockIdx.y, j);
+}
+
+template <class R, int SCH>
+void launch_node_sch(const Tables& T, dim3 grid, const R* f, R* out, const R* ghost, hipStream_t s) {
+  if (T.nf == 8)
+    hipLaunchKernelGGL((step_node_kernel<R, SCH, false>), grid, dim3(256), 0, s, T, f, out, ghost);
+  else
+    hipLaunchKernelGGL((step_node_kernel<R, SCH, true>), grid, dim3(256), 0, s, T, f, out, ghost);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,22 +178,24 @@ __global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restric
   eq_setup(T, rho, ux, uy, E, ec);
   const double ct = T.cth[j], st = T.sth[j];
   const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
-  double acc[4][12];
+  // one kind at a time (12 accumulators live, not 48): M, M*, Delta, Delta*
+  int slot = 0;
+#pragma unroll 1
+  for (int kind = 0; kind < 4; ++kind) {
+    if (!((kinds >> kind) & 1)) continue;
+    const bool dev = kind >= 2;                    // moments of f - f^eq
+    const double sr = (kind & 1) ? ur : 0.0;       // central: velocities relative to u
+    const double sq = (kind & 1) ? ut : 0.0;
+    double o[12];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 12; ++c) o[c] = 0.0;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[a][c] = 0.0;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const double feq = q == 0 ? ec.rF[0] * ec.A0 : eq_val(ec, k_of(q), d_of(q));
-    const double vr = vx_q(q) * ct + vy_q(q) * st, vt = -vx_q(q) * st + vy_q(q) * ct;
-#pragma unroll
-    for (int kind = 0; kind < 4; ++kind) {
-      const double w = kind < 2 ? fl[q] : fl[q] - feq;
-      const double a = (kind & 1) ? vr - ur : vr;
-      const double b = (kind & 1) ? vt - ut : vt;
+    for (int q = 0; q < NQ; ++q) {
+      const double feq = q == 0 ? ec.rF[0] * ec.A0 : eq_val(ec, k_of(q), d_of(q));
+      const double w = dev ? fl[q] - feq : fl[q];
+      const double a = vx_q(q) * ct + vy_q(q) * st - sr;
+      const double b = -vx_q(q) * st + vy_q(q) * ct - sq;
       const double h = 0.5 * (a * a + b * b);
-      double* o = acc[kind];
       const double wa = w * a, wb = w * b, waa = wa * a, wab = wa * b, wbb = wb * b;
       o[0] += waa;
       o[1] += wab;
@@ -193,13 +210,8 @@ __global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restric
       o[10] += h * wab;
       o[11] += h * wbb;
     }
-  }
-  int slot = 0;
 #pragma unroll
-  for (int kind = 0; kind < 4; ++kind) {
-    if (!((kinds >> kind) & 1)) continue;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) out[((size_t)slot * 12 + c) * plane + c0] = acc[kind][c];
+    for (int c = 0; c < 12; ++c) out[((size_t)slot * 12 + c) * plane + c0] = o[c];
     ++slot;
   }
 }
@@ -317,7 +329,14 @@ hipError_t launch_ghost(const Tables& T, const BCdev& bc, const void* f, void* g
 template <class R>
 hipError_t launch_step_node(const Tables& T, const void* f, void* out, const void* ghost, hipStream_t s) {
   dim3 grid((T.nth + 255) / 256, T.nr);
-  hipLaunchKernelGGL(step_node_kernel<R>, grid, dim3(256), 0, s, T, (const R*)f, (R*)out, (const R*)ghost);
+  const R* fi = (const R*)f;
+  const R* gh = (const R*)ghost;
+  switch (T.scheme) {
+    case SCH_WB: launch_node_sch<R, SCH_WB>(T, grid, fi, (R*)out, gh, s); break;
+    case SCH_LW: launch_node_sch<R, SCH_LW>(T, grid, fi, (R*)out, gh, s); break;
+    case SCH_UPWIND2: launch_node_sch<R, SCH_UPWIND2>(T, grid, fi, (R*)out, gh, s); break;
+    default: launch_node_sch<R, SCH_MWB>(T, grid, fi, (R*)out, gh, s);
+  }
   return hipGetLastError();
 }
 

@@ -527,9 +527,9 @@ bool strip_supported(const Tables& T) {
   // plus the lane offset, kept below 9 planes) must stay below 2^31, the OOB
   // marker; the lanes of one strip must be distinct columns
   const double plane_bytes = 4.0 * T.nr * (double)T.nth;
-  // the strip kernel wraps theta without rotating the velocity index: full
-  // annulus only
-  return std::is_same<R, float>::value && T.nf == 8 && T.nth >= WAVE &&
+  // the strip kernel wraps theta without rotating the velocity index (full
+  // annulus only) and carries the MWB scheme only
+  return std::is_same<R, float>::value && T.nf == 8 && T.scheme == SCH_MWB && T.nth >= WAVE &&
          9.0 * plane_bytes < 2147483647.0;
 }
 

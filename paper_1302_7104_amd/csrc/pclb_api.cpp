@@ -82,6 +82,11 @@ int validate(const pclb_config* c, std::string& why) {
     why = "adjoint_tie must be in [0, 1e-2)";
     return PCLB_EINVAL;
   }
+  if (c->scheme < PCLB_SCHEME_MWB || c->scheme > PCLB_SCHEME_UPWIND2) { why = "unknown scheme"; return PCLB_EINVAL; }
+  if (c->relaxation != PCLB_RELAX_ANALYTIC && c->relaxation != PCLB_RELAX_EULER) {
+    why = "unknown relaxation";
+    return PCLB_EINVAL;
+  }
   double dr = (c->r2 - c->r1) / (c->n_r - 1);
   double dth = sector_dth(c);
   double vmax = speed(NK);
@@ -182,7 +187,10 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   T.nf = cfg->n_f;
   T.dt_dr = cfg->dt / c->dr;
   T.dt_dth = cfg->dt / c->dth;
-  T.e = std::exp(-cfg->dt / cfg->tau);
+  // both relaxations are f^eq + (f - f^eq) e: Eq. operator1_new with
+  // e = exp(-dt/tau), Eq. operator1_old with e = 1 - dt/tau
+  T.e = cfg->relaxation == PCLB_RELAX_EULER ? 1.0 - cfg->dt / cfg->tau : std::exp(-cfg->dt / cfg->tau);
+  T.scheme = cfg->scheme;
   T.cth = c->d_geom;
   T.sth = c->d_geom + nth;
   T.rinv = c->d_geom + 2 * nth;
@@ -350,6 +358,7 @@ int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* 
   if (!c) return PCLB_EINVAL;
   if (!f_t || !lam_next || !lam_out || lam_out == lam_next || lam_out == f_t)
     return fail(c, PCLB_EINVAL, "three non-null buffers, lam_out distinct from the inputs");
+  if (c->cfg.scheme != PCLB_SCHEME_MWB) return fail(c, PCLB_EINVAL, "the adjoint covers the MWB scheme only");
   hipError_t e = c->cfg.precision == 32
                      ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream)
                      : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream);

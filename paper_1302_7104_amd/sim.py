@@ -26,13 +26,16 @@ class Sim:
     """One annulus, one precision, one device.
 
     ``problem`` is any object with nr, nth, r1, r2, tau, dt, bc_kind, bc_par
-    (e.g. a ``workloads.Problem``).  ``strip_*`` set the launch shape of the
-    strip kernel (0: default) and ``adjoint_tie`` the tie threshold of the
-    adjoint (0: the precision's default)."""
+    and optionally nf (e.g. a ``workloads.Problem``).  ``strip_*`` set the
+    launch shape of the strip kernel (0: default), ``adjoint_tie`` the tie
+    threshold of the adjoint (0: the precision's default), ``scheme`` and
+    ``relaxation`` the convection scheme and the relaxation form (the
+    paper's combined scheme by default)."""
 
     def __init__(self, problem, precision: int = 32, kernel: int = N.KERNEL_AUTO,
                  device: str | torch.device = "cuda:0", strip_chunk: int = 0,
-                 strip_order: int = N.ORDER_DEFAULT, adjoint_tie: float = 0.0):
+                 strip_order: int = N.ORDER_DEFAULT, adjoint_tie: float = 0.0,
+                 scheme: int = N.SCHEME_MWB, relaxation: int = N.RELAX_ANALYTIC):
         if precision not in (32, 64):
             raise ValueError("precision must be 32 or 64")
         self.L = N.lib()
@@ -46,8 +49,7 @@ class Sim:
         self.nr, self.nth = problem.nr, problem.nth
         self.cfg = N.Config(problem.nr, problem.nth, problem.r1, problem.r2, problem.tau,
                             problem.dt, 8, getattr(problem, "nf", 8), precision, 1, kernel,
-                            strip_chunk, strip_order,
-                            adjoint_tie)
+                            strip_chunk, strip_order, adjoint_tie, scheme, relaxation)
         ctx = ctypes.c_void_p()
         N.check(self.L.pclb_create(ctypes.byref(self.cfg), ctypes.byref(ctx)), None)
         self.ctx = ctx

@@ -19,7 +19,7 @@ struct Setup {
   Tables T{};
   BCdev bc{};
   Setup(int nr, int nth, int nf, double r1, double r2, double tau, double dt, const int32_t* kind,
-        const double* par)
+        const double* par, int scheme = SCH_MWB, int relax = 0)
       : cth(nth), sth(nth), rinv(nr), wA(nr) {
     const double PI = 3.14159265358979323846;
     const double dr = (r2 - r1) / (nr - 1), dth = 2.0 * PI * nf / (8.0 * nth);
@@ -33,7 +33,8 @@ struct Setup {
     T.nf = nf;
     T.dt_dr = dt / dr;
     T.dt_dth = dt / dth;
-    T.e = std::exp(-dt / tau);
+    T.e = relax == 1 ? 1.0 - dt / tau : std::exp(-dt / tau);
+    T.scheme = scheme;
     T.cth = cth.data();
     T.sth = sth.data();
     T.rinv = rinv.data();
@@ -71,8 +72,8 @@ void fill_ghosts(const Setup& S, const R* cur, std::vector<R>& ghost) {
 
 template <class R>
 void run(int nr, int nth, int nf, double r1, double r2, double tau, double dt, const int32_t* kind,
-         const double* par, const R* fin, R* fout, int nsteps) {
-  Setup S(nr, nth, nf, r1, r2, tau, dt, kind, par);
+         const double* par, const R* fin, R* fout, int nsteps, int scheme, int relax) {
+  Setup S(nr, nth, nf, r1, r2, tau, dt, kind, par, scheme, relax);
   const Tables& T = S.T;
   const std::vector<double>& cth = S.cth;
   const std::vector<double>& sth = S.sth;
@@ -98,7 +99,12 @@ void run(int nr, int nth, int nf, double r1, double r2, double tau, double dt, c
           else if (t >= nth) { t -= nth; qq = rot_q(q, (8 - nf) & 7); }
           return cur[qq * plane + (size_t)i * nth + t];
         };
-        node_update<R>(T, i, j, fc, row, col, res);
+        switch (scheme) {
+          case SCH_WB: node_update<R, SCH_WB>(T, i, j, fc, row, col, res); break;
+          case SCH_LW: node_update<R, SCH_LW>(T, i, j, fc, row, col, res); break;
+          case SCH_UPWIND2: node_update<R, SCH_UPWIND2>(T, i, j, fc, row, col, res); break;
+          default: node_update<R, SCH_MWB>(T, i, j, fc, row, col, res);
+        }
         for (int q = 0; q < NQ; ++q) nxt[q * plane + (size_t)i * nth + j] = res[q];
       }
     cur.swap(nxt);
@@ -135,12 +141,16 @@ extern "C" int emu_adjoint_step(int32_t nr, int32_t nth, double r1, double r2, d
   return 0;
 }
 
+// scheme: SCH_*; relax: 0 analytic, 1 forward Euler
 extern "C" int emu_steps(int32_t nr, int32_t nth, double r1, double r2, double tau, double dt,
                          const int32_t* kind, const double* par, int32_t precision,
-                         const void* fin, void* fout, int32_t nsteps, int32_t nf) {
+                         const void* fin, void* fout, int32_t nsteps, int32_t nf, int32_t scheme,
+                         int32_t relax) {
   if (precision == 64)
-    run<double>(nr, nth, nf, r1, r2, tau, dt, kind, par, (const double*)fin, (double*)fout, nsteps);
+    run<double>(nr, nth, nf, r1, r2, tau, dt, kind, par, (const double*)fin, (double*)fout, nsteps,
+                scheme, relax);
   else
-    run<float>(nr, nth, nf, r1, r2, tau, dt, kind, par, (const float*)fin, (float*)fout, nsteps);
+    run<float>(nr, nth, nf, r1, r2, tau, dt, kind, par, (const float*)fin, (float*)fout, nsteps,
+               scheme, relax);
   return 0;
 }

@@ -2,7 +2,8 @@
 // the device arithmetic (test infrastructure, built with hipcc for the host
 // only and run by tests/test_sanitizers.py): runs the emulated step and
 // adjoint step of tests/native/emulate.cpp in both precisions with each
-// radial boundary kind, on the full annulus and on sectors.
+// radial boundary kind, on the full annulus and on sectors, and every
+// convection scheme with forward-Euler relaxation.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -17,7 +18,9 @@ static double run_case(const int32_t* kind, const double* par, int prec, int nf)
   // a smooth positive state: f^eq-like magnitudes with a ripple
   for (size_t q = 0; q < ns; ++q) f[q] = (R)(0.02 * (1.0 + 0.1 * std::sin(0.01 * (double)q)));
   for (size_t q = 0; q < ns; ++q) lam[q] = (R)std::cos(0.003 * (double)q);
-  emu_steps(nr, nth, 0.5, 1.5, 2e-3, 1e-3, kind, par, prec, f.data(), fo.data(), 2, nf);
+  for (int sch = 1; sch < 4; ++sch)
+    emu_steps(nr, nth, 0.5, 1.5, 2e-3, 1e-3, kind, par, prec, f.data(), fo.data(), 2, nf, sch, 1);
+  emu_steps(nr, nth, 0.5, 1.5, 2e-3, 1e-3, kind, par, prec, f.data(), fo.data(), 2, nf, 0, 0);
   emu_adjoint_step(nr, nth, 0.5, 1.5, 2e-3, 1e-3, kind, par, prec, prec == 64 ? 1e-13 : 1e-6,
                    fo.data(), lam.data(), lo.data(), nf);
   return (double)fo[ns / 2] + (double)lo[ns / 3];

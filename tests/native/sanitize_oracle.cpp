@@ -17,6 +17,7 @@ struct OrGrid {
   double bc_par[2][4];
   int32_t terms;
   int32_t nf;
+  int32_t scheme, relax;
 };
 
 extern "C" {
@@ -35,8 +36,8 @@ void or_init_feq(const OrGrid* g, const double* rho, const double* ur, const dou
                  const double* T, double* f);
 void or_fields(const OrGrid* g, const double* f, double* rho, double* ur, double* ut, double* T);
 void or_diagnostics(const OrGrid* g, const double* f, double* out);
-void or_adjoint_step(const OrGrid* g, const double* f_t, const double* lam_next, double tie_eps,
-                     double* out);
+int or_adjoint_step(const OrGrid* g, const double* f_t, const double* lam_next, double tie_eps,
+                    double* out);
 void or_adjoint_init(const OrGrid* g, const double* rho, const double* ur, const double* ut,
                      const double* T, const double* lam, double* d_rho, double* d_ur, double* d_ut,
                      double* d_T);
@@ -72,7 +73,8 @@ int main() {
   const int32_t kinds[3][2] = {{0, 0}, {1, 2}, {2, 1}};
   for (const auto& kd : kinds)
   for (int nf : {8, 1, 3}) {
-    OrGrid g{nr, nth, 0.5, 1.5, 2e-3, 1e-3, {kd[0], kd[1]}, {{0.2, 0, 0, 0}, {1.05, 0.02, 0.01, 0.95}}, 7, nf};
+    OrGrid g{nr, nth, 0.5, 1.5, 2e-3, 1e-3, {kd[0], kd[1]}, {{0.2, 0, 0, 0}, {1.05, 0.02, 0.01, 0.95}}, 7, nf,
+             0, nf == 3 ? 1 : 0};
     if (kd[0] == 1) { g.bc_par[0][0] = 1.1; g.bc_par[0][1] = 0.05; g.bc_par[0][2] = 0.0; g.bc_par[0][3] = 1.0; }
     std::vector<double> rho(n), ur(n), ut(n), T(n);
     for (int i = 0; i < nr; ++i)
@@ -92,7 +94,17 @@ int main() {
     or_fields(&g, f1.data(), rho.data(), ur.data(), nullptr, T.data());
     or_diagnostics(&g, f1.data(), d.data());
     for (size_t q = 0; q < ns; ++q) lam[q] = std::sin(0.001 * (double)q);
-    or_adjoint_step(&g, f1.data(), lam.data(), 1e-13, lo.data());
+    if (or_adjoint_step(&g, f1.data(), lam.data(), 1e-13, lo.data()) != 0) return 4;
+    // every convection scheme through the step and the sampled step
+    for (int sch = 1; sch < 4; ++sch) {
+      OrGrid gs = g;
+      gs.scheme = sch;
+      std::vector<double> fs(ns);
+      if (or_step(&gs, f.data(), fs.data(), 2) != 0) return 5;
+      or_step_sample(&gs, f.data(), nodes, 3, smp.data());
+      sink += fs[ns / 4] + smp[1];
+      if (or_adjoint_step(&gs, f1.data(), lam.data(), 1e-13, lo.data()) != -1) return 6;
+    }
     std::vector<double> dr(n), du(n), dv(n), dT(n);
     or_adjoint_init(&g, rho.data(), ur.data(), ut.data(), T.data(), lam.data(), dr.data(), du.data(),
                     dv.data(), dT.data());

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def cfg(**kw):
     base = dict(n_r=64, n_theta=128, r1=1.0, r2=2.0, tau=1e-4, dt=1e-3, n_i=8, n_f=8,
                 precision=64, fp64_collision=1, kernel=0, strip_chunk=0, strip_order=0,
-                adjoint_tie=0.0)
+                adjoint_tie=0.0, scheme=0, relaxation=0)
     base.update(kw)
     return N.Config(*[base[k] for k, _ in N.Config._fields_])
 
@@ -54,6 +54,7 @@ def test_cfl_dt_matches_workload_rule():
     (dict(n_f=9), -1), (dict(n_f=1, dt=2e-3), -2),
     (dict(precision=16), -1), (dict(kernel=7), -1), (dict(dt=0.01), -2),
     (dict(fp64_collision=0), -1), (dict(adjoint_tie=-1.0), -1), (dict(adjoint_tie=0.5), -1),
+    (dict(scheme=4), -1), (dict(scheme=-1), -1), (dict(relaxation=2), -1),
 ])
 def test_create_rejects_invalid_config(kw, code):
     L = N.lib()

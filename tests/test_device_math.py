@@ -27,21 +27,21 @@ def emu():
     L = ctypes.CDLL(LIB)
     L.emu_steps.argtypes = [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 4 + [
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
-        ctypes.c_int32]
+        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.emu_adjoint_step.argtypes = [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 4 + [
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     return L
 
 
-def run_emu(L, P, f0, steps, precision):
+def run_emu(L, P, f0, steps, precision, scheme=0, relax=0):
     dt = np.float64 if precision == 64 else np.float32
     fin = np.ascontiguousarray(f0, dtype=dt)
     fout = np.empty_like(fin)
     kind = (ctypes.c_int32 * 2)(*P.bc_kind)
     par = (ctypes.c_double * 8)(*[float(x) for s in P.bc_par for x in (list(s) + [0] * 4)[:4]])
     L.emu_steps(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, kind, par, precision,
-                fin.ctypes.data, fout.ctypes.data, steps, P.nf)
+                fin.ctypes.data, fout.ctypes.data, steps, P.nf, scheme, relax)
     return fout.astype(np.float64)
 
 
@@ -141,3 +141,26 @@ def test_axis_columns_take_the_octant_below(emu):
         want, _ = O.step(g, f0, 3)
         got = run_emu(emu, P, f0, 3, 64)
         assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-14, nth
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+def test_emulated_comparison_schemes_match_oracle(emu, scheme, relax):
+    """The Warming-Beam, Lax-Wendroff and second-order upwind convection and
+    the forward-Euler relaxation, as the node kernel computes them, against
+    the oracle's printed forms.  tau is 2.4 dt: the forward-Euler relaxation
+    amplifies by |1 - dt/tau| per step and is unstable beyond dt/tau = 2 (the
+    stiffness the analytic relaxation removes)."""
+    P, F = W.smooth_random(9, 24, seed=3, amp=0.05, bc=(W.WALL, W.INFLOW),
+                           bc_par=((0.2, 0, 0, 0), (1.1, 0.05, 0.02, 1.05)), tau=2e-2)
+    g = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par, nf=P.nf,
+               scheme=scheme, relax=relax)
+    f0 = O.init_feq(g, **F) * (1 + W.noise((33, P.nr, P.nth), 1e-3, 4))
+    want, _ = O.step(g, f0, 4)
+    got64 = run_emu(emu, P, f0, 4, 64, scheme, relax)
+    assert np.linalg.norm(got64 - want) / np.linalg.norm(want) <= 1e-13
+    got32 = run_emu(emu, P, f0, 4, 32, scheme, relax)
+    assert np.linalg.norm(got32 - want) / np.linalg.norm(want) <= 1e-6
+    # the schemes differ from MWB (and from each other) at this size
+    mwb, _ = O.step(O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, P.bc_kind, P.bc_par, relax=relax), f0, 4)
+    assert np.linalg.norm(want - mwb) / np.linalg.norm(mwb) > 1e-6
