@@ -106,7 +106,9 @@ PCLB_HD inline void ghost_adjoint_column(const Tables& T, const BCdev& bc, const
 // ---------------------------------------------------------------------------
 // Node adjoint of node (i, j): gather over every output whose stencil holds
 // the node.
-template <class R>
+// SECTOR: the grid is a sector (n_f < 8) whose ends rotate the direction
+// index; without it the rotations are compiled out.
+template <class R, bool SECTOR = true>
 PCLB_HD inline void adjoint_node(const Tables& T, const R* __restrict__ f, const R* __restrict__ lam,
                                  const R* __restrict__ ghost, const double* __restrict__ gm,
                                  double tie, int i, int j, R* __restrict__ out) {
@@ -152,7 +154,7 @@ PCLB_HD inline void adjoint_node(const Tables& T, const R* __restrict__ f, const
 #pragma unroll
   for (int s = 0; s < 5; ++s) {
     int t = j + s - 2;
-    rot[s] = t < 0 ? s_lo : (t >= nth ? s_hi : 0);
+    rot[s] = !SECTOR ? 0 : t < 0 ? s_lo : (t >= nth ? s_hi : 0);
     t = t < 0 ? t + nth : (t >= nth ? t - nth : t);
     jj[s] = t;
     cs[s] = T.cth[t];

@@ -164,19 +164,20 @@ PCLB_HD inline double eq_val(const EqCoef& c, int k, int d) {
 // the end), summed per pair of opposite directions (d, d+4), d = 0..3: with
 // sp_k = f_{k,d} + f_{k,d+4} and sm_k = f_{k,d} - f_{k,d+4},
 //   rho_d = sum_k sp_k, j_d = sum_k v_k e_d sm_k, eps_d = sum_k v_k^2 sp_k
-// (e_d's zero components included, so that the same operations run for every
-// d); the four partials are then added in the order d = 0, 1, 2, 3 and the
-// rest velocity last.  Every kernel sums in exactly this order.
+// the four partials are then added in the order d = 0, 1, 2, 3 and the rest
+// velocity last.  Every kernel sums in exactly this order.
 PCLB_HD inline void d4_partial(int d4, const double* fp, const double* fm, double* P) {
-  const double ex = cos_d(d4), ey = sin_d(d4);
   double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
 #pragma unroll
   for (int k = 1; k <= NK; ++k) {
     const double sp = fp[k - 1] + fm[k - 1];
     const double sm = fp[k - 1] - fm[k - 1];
     r += sp;
-    jx += (speed(k) * ex) * sm;
-    jy += (speed(k) * ey) * sm;
+    // a zero component adds nothing (skipping it leaves every sum unchanged
+    // and saves the constants and operations in the kernels, where d4 is
+    // known at compile time)
+    if (cos_d(d4) != 0.0) jx += (speed(k) * cos_d(d4)) * sm;
+    if (sin_d(d4) != 0.0) jy += (speed(k) * sin_d(d4)) * sm;
     eps += (speed(k) * speed(k)) * sp;
   }
   P[0] = r;
@@ -217,46 +218,29 @@ PCLB_HD inline void node_macros(const double* f, double& rho, double& ux, double
   combine_partials(P, f[0], rho, ux, uy, E);
 }
 
-// Coefficients of the analytic relaxation (Eq. operator1_new) of one node:
-// the relaxed value e f + (1 - e) f^eq of velocity (k, d) with
-// f^eq = rho F_k P(w), w = v_k p_d, p_d = u . e_d, written from the powers of
-// p_d so that the four speeds of a direction share them:
-//   (1 - e) f^eq_{k,d}    = s_k (even + odd),  (1 - e) f^eq_{k,d+4} = s_k (even - odd),
-//   even = A0 + v_k^2 (A2 p^2) + v_k^4 (A4 p^4),  odd = v_k (A1 p) + v_k^3 (A3 p^3),
-// s_k = (1 - e) rho F_k; the rest velocity's share is s_0 = (1 - e) rho F_0 A0.
-struct RelaxCoef {
-  double s[NK + 1];
-  double A0;
-  double b[4][4];      // per direction pair d = 0..3: A1 p, A2 p^2, A3 p^3, A4 p^4
-};
-
-PCLB_HD inline void relax_setup(const EqCoef& c, double one_m_e, RelaxCoef& rc) {
-  rc.s[0] = one_m_e * (c.rF[0] * c.A0);
-#pragma unroll
-  for (int k = 1; k <= NK; ++k) rc.s[k] = one_m_e * c.rF[k];
-  rc.A0 = c.A0;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    const double p = c.p[d], p2 = p * p;
-    rc.b[d][0] = c.A1 * p;
-    rc.b[d][1] = c.A2 * p2;
-    rc.b[d][2] = c.A3 * (p2 * p);
-    rc.b[d][3] = c.A4 * (p2 * p2);
-  }
+// Relaxed values of the opposite pair (k, d) and (k, d + 4), d = 0..3
+// (Eq. operator1_new): f^eq + (f - f^eq) e written as e f + (1 - e) f^eq,
+// with f^eq = rho F_k P(+-w) and P split into its even and odd parts in
+// w = v_k pd, pd = u . e_d (the caller passes c.p[d], or its negative to hand
+// the pair over in the order (d + 4, d); negation is exact, so both orders
+// give the same two values).  In double: the caller rounds once, after the
+// convection terms.  one_m_e = 1 - e.
+template <int K>
+PCLB_HD inline void relax_pair(const EqCoef& c, double e, double one_m_e, double pd, double fp,
+                               double fm, double& rp, double& rm) {
+  const double w = speed(K) * pd;
+  const double w2 = w * w;
+  const double ev = c.A0 + w2 * (c.A2 + w2 * c.A4);
+  const double od = w * (c.A1 + w2 * c.A3);
+  const double s = one_m_e * c.rF[K];
+  const double gp = s * (ev + od), gm = s * (ev - od);
+  rp = fma(fp, e, gp);
+  rm = fma(fm, e, gm);
 }
 
-// Relaxed values of the opposite pair (k, d) and (k, d + 4) from the pair's
-// coefficients b = b[d] with the odd ones (b[0], b[2]) multiplied by sg (+1;
-// -1 hands the pair over in the order (d + 4, d)).  In double.
-template <int K>
-PCLB_HD inline void relax_pair(double s, double A0, double b0, double b1, double b2, double b3,
-                               double e, double fp, double fm, double& rp, double& rm) {
-  constexpr double v = speed(K), v2 = v * v, v3 = v2 * v, v4 = v2 * v2;
-  const double ev = fma(v4, b3, fma(v2, b1, A0));
-  const double od = fma(v3, b2, v * b0);
-  const double t = s * ev;
-  rp = fma(fp, e, fma(s, od, t));
-  rm = fma(fm, e, fma(-s, od, t));
+// The rest velocity: (1 - e) rho F_0 A0 + e f_0.
+PCLB_HD inline double relax_rest_share(const EqCoef& c, double one_m_e) {
+  return one_m_e * (c.rF[0] * c.A0);
 }
 
 template <class R>
@@ -429,22 +413,20 @@ PCLB_HD inline void node_update_put(const Tables& T, int i, int j, const R* fc, 
   node_macros(fd, rho, ux, uy, E);
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
-  RelaxCoef rc;
-  relax_setup(ec, 1.0 - T.e, rc);
-  const double e = T.e;
-  put(0, relax_rest<R>(rc.s[0], e, fd[0]));       // rest velocity: no convection
+  const double e = T.e, ome = 1.0 - T.e;
+  put(0, relax_rest<R>(relax_rest_share(ec, ome), e, fd[0]));   // rest velocity: no convection
   DirGeom<R> G;
   dir_geometry(ct, st, octant_of(j, T.nth, T.nf), T.dt_dr, T.dt_dth, G);
   const R rinv = (R)T.rinv[i];
   R atr[4];
   for (int d = 0; d < 4; ++d) atr[d] = G.at[d] * rinv;
-  for_k<1>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
+  // direction pairs outer, speeds inner
 #pragma unroll
-    for (int d4 = 0; d4 < 4; ++d4) {
+  for (int d4 = 0; d4 < 4; ++d4) {
+    for_k<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
       double rel[2];
-      relax_pair<k>(rc.s[k], rc.A0, rc.b[d4][0], rc.b[d4][1], rc.b[d4][2], rc.b[d4][3], e,
-                       fd[qidx(k, d4)], fd[qidx(k, d4 + 4)], rel[0], rel[1]);
+      relax_pair<k>(ec, e, ome, ec.p[d4], fd[qidx(k, d4)], fd[qidx(k, d4 + 4)], rel[0], rel[1]);
       R aCr, Kr, aCt, Kt;
       courant<R>((R)speed(k), G.ar[d4], aCr, Kr);
       courant<R>((R)speed(k), atr[d4], aCt, Kt);
@@ -466,8 +448,8 @@ PCLB_HD inline void node_update_put(const Tables& T, int i, int j, const R* fc, 
           put(q, (R)((rel[h] - (double)tr) - (double)tt));
         }
       }
-    }
-  });
+    });
+  }
 }
 
 // The same with the results in res[0..NQ-1].

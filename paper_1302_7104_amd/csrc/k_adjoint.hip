@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(128) ghost_adjoint_kernel(Tables T, BCdev bc, 
 // ---------------------------------------------------------------------------
 // Node adjoint: one thread per node m, gather over every output whose stencil
 // holds m.
-template <class R>
+template <class R, bool SECTOR>
 __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __restrict__ f,
                                                            const R* __restrict__ lam,
                                                            const R* __restrict__ ghost,
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(128) adjoint_node_kernel(Tables T, const R* __
                                                            double tie, R* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= T.nth) return;
-  adjoint_node<R>(T, f, lam, ghost, gm, tie, blockIdx.y, j, out);
+  adjoint_node<R, SECTOR>(T, f, lam, ghost, gm, tie, blockIdx.y, j, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -78,8 +78,13 @@ hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const
                      (const R*)f, (const R*)lam, (const R*)ghost, tie, gm);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adjoint_node_kernel<R>, dim3((T.nth + 127) / 128, T.nr), dim3(128), 0, s, T,
-                     (const R*)f, (const R*)lam, (const R*)ghost, (const double*)gm, tie, (R*)lam_out);
+  const dim3 grid((T.nth + 127) / 128, T.nr);
+  if (T.nf == 8)
+    hipLaunchKernelGGL((adjoint_node_kernel<R, false>), grid, dim3(128), 0, s, T, (const R*)f,
+                       (const R*)lam, (const R*)ghost, (const double*)gm, tie, (R*)lam_out);
+  else
+    hipLaunchKernelGGL((adjoint_node_kernel<R, true>), grid, dim3(128), 0, s, T, (const R*)f,
+                       (const R*)lam, (const R*)ghost, (const double*)gm, tie, (R*)lam_out);
   return hipGetLastError();
 }
 

@@ -215,8 +215,6 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   combine_partials(P, rest, rho, ux, uy, E);
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
-  RelaxCoef rc;
-  relax_setup(ec, X.ome, rc);
   // 1/r of this row from lane (i - i_begin) of rinv_lane: a table load here
   // would be waited for in order behind every look-ahead load and store in
   // flight
@@ -224,7 +222,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   const uint32_t ovoff = X.store ? (uint32_t)(i * X.nth) * 4u + X.col4 : OOB;
   const uint32_t vb = row_off(X, i + NS - 2, moreN), vf = row_off(X, i + NS, moreN);
   if constexpr (W == 0) {            // rest velocity: relaxation only, one row ahead
-    const float res = relax_rest<float>(rc.s[0], X.e, (double)r0);
+    const float res = relax_rest<float>(relax_rest_share(ec, X.ome), X.e, (double)r0);
     store_slot<1>(X, 0, ovoff, res);
     r0 = load_slot<EDGE, 1>(X, 0, 0, i + 1, row_off(X, i + 1, more), more);
   }
@@ -239,8 +237,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
     double rel[2];
     // with the members swapped the odd coefficients change sign, exactly
     const double sg = UNI ? RL.sg[pl] : 1.0;
-    relax_pair<k>(rc.s[k], rc.A0, sg * rc.b[d4][0], rc.b[d4][1], sg * rc.b[d4][2],
-                         rc.b[d4][3], X.e, (double)c0, (double)c1, rel[0], rel[1]);
+    relax_pair<k>(ec, X.e, X.ome, sg * ec.p[d4], (double)c0, (double)c1, rel[0], rel[1]);
     float aCr, Kr, aCt, Kt;
     courant<float>((float)speed(k), G.ar[d4], aCr, Kr);
     courant<float>((float)speed(k), G.at[d4] * rinv, aCt, Kt);
@@ -455,8 +452,11 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
 
 }  // namespace
 
+// Two waves per SIMD (at most 256 registers per lane): left to itself the
+// compiler spends a few accumulation registers beyond that on the uniform
+// variant and drops to one wave.
 template <int NSPLIT, bool MIXED>
-__global__ void __launch_bounds__(WAVE * NSPLIT)
+__global__ void __launch_bounds__(WAVE * NSPLIT) __attribute__((amdgpu_waves_per_eu(2)))
 step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out,
                   const float* __restrict__ ghost, int chunk_rows, int n_strips, int xcd_order) {
   __shared__ double lds[NSPLIT > 1 ? 2 * 17 * 64 : 1];
