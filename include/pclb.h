@@ -173,6 +173,18 @@ int pclb_init_state(pclb_ctx* ctx, const double* rho, const double* u_r,
  * Asynchronous. */
 int pclb_step(pclb_ctx* ctx, int64_t n);
 
+/* pclb_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same steps, bit for bit, with the radial ghost layers held in a static
+ * scratch array of the library (16 MiB per GPU, reserved while the library is
+ * loaded) instead of the context's buffer.  Calls no allocating routine.
+ * Returns PCLB_EINVAL if the ghost layers (4 * 33 * n_theta elements of the
+ * state type) exceed the array, i.e. n_theta > 31775 at precision 32 or
+ * n_theta > 15887 at precision 64.  Every call on one GPU, from any context,
+ * uses that GPU's one array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must not be issued. */
+int pclb_step_static(pclb_ctx* ctx, int64_t n);
+
 /* One step from an arbitrary caller buffer f_in to f_out (both device
  * buffers of the context's element type and size; they must not overlap).
  * Used by checkpoint-recompute.  Does not touch the bound buffers or the step

@@ -14,6 +14,15 @@
 
 using namespace pclb;
 
+// Scratch of pclb_step_static: the radial ghost layers (4 * 33 * n_theta
+// elements of the state type) in a file-scope device array, so that the entry
+// point needs no allocation.  Every GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the per-device
+// address hipGetSymbolAddress returns (the array's name is a host-side
+// stand-in, not a device address).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
 struct pclb_ctx {
   pclb_config cfg{};
   int device = 0;
@@ -34,6 +43,7 @@ struct pclb_ctx {
   double* d_diag = nullptr;     // 8 doubles for the synchronizing variant
   int* d_flag = nullptr;        // init validation flag
   double* d_gm = nullptr;       // adjoint: ghost moment cotangents 2*2*4*nth
+  void* d_scratch = nullptr;    // this device's copy of the static scratch array
   std::string err;
 };
 
@@ -116,6 +126,7 @@ hipError_t step_once(pclb_ctx* c, const void* in, void* out, void* ghost) {
                                 : do_step<double>(c, in, out, ghost);
 }
 
+size_t ghost_bytes(const pclb_ctx* c) { return 4 * (size_t)NQ * c->cfg.n_theta * elem_size(c); }
 
 }  // namespace
 
@@ -163,6 +174,13 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
     h[2 * nth + i] = 1.0 / r;
     double w = (i == 0 || i == nr - 1) ? 0.5 : 1.0;
     h[2 * nth + nr + i] = r * w * c->dr * c->dth;
+  }
+  // this device's address of the static scratch array (used by pclb_step_static)
+  e = hipGetSymbolAddress(&c->d_scratch, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) {
+    delete[] h;
+    delete c;
+    return fail(nullptr, PCLB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
   }
   size_t es = cfg->precision == 32 ? 4 : 8;
   bool ok = hipMalloc(&c->d_geom, ngeom * sizeof(double)) == hipSuccess &&
@@ -278,6 +296,27 @@ int pclb_step(pclb_ctx* c, int64_t n) {
   if (n < 0) return fail(c, PCLB_EINVAL, "negative step count");
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e = step_once(c, c->f[c->cur], c->f[1 - c->cur], c->d_ghost);
+    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    c->cur = 1 - c->cur;
+    ++c->steps;
+  }
+  return PCLB_OK;
+}
+
+int pclb_step_static(pclb_ctx* c, int64_t n) {
+  if (!c) return PCLB_EINVAL;
+  if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
+  if (n < 0) return fail(c, PCLB_EINVAL, "negative step count");
+  if (ghost_bytes(c) > STATIC_SCRATCH_BYTES) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "ghost layers need %zu bytes, above the %zu-byte static scratch (n_theta <= %zu "
+                  "at this precision)",
+                  ghost_bytes(c), STATIC_SCRATCH_BYTES, STATIC_SCRATCH_BYTES / (4 * NQ * elem_size(c)));
+    return fail(c, PCLB_EINVAL, buf);
+  }
+  for (int64_t s = 0; s < n; ++s) {
+    hipError_t e = step_once(c, c->f[c->cur], c->f[1 - c->cur], c->d_scratch);
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
     c->cur = 1 - c->cur;
     ++c->steps;
