@@ -397,6 +397,28 @@ PCLB_HD inline void for_k(Fn&& fn) {
   }
 }
 
+// New value of velocity q (direction d) of one node from its relaxed value
+// rel (double), its centre value c and the Courant factors, the neighbours
+// read through row(q, di) / col(q, dj): the scheme's two convection terms in
+// the state type, subtracted in double, one rounding.
+template <class R, int SCH, class RowFn, class ColFn>
+PCLB_HD inline R velocity_update(const DirGeom<R>& G, int d, int q, double rel, R c, R aCr, R Kr,
+                                 R aCt, R Kt, RowFn& row, ColFn& col) {
+  const int sr = ((G.rback >> d) & 1u) ? -1 : 1;   // upwind offset in r
+  const int sc = ((G.tback >> d) & 1u) ? -1 : 1;   // upwind offset in theta
+  if constexpr (SCH == SCH_MWB) {
+    return mwb_update<R>(rel, c, aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt, col(q, sc),
+                         col(q, 2 * sc));
+  } else {
+    // the downwind neighbours only matter to Lax-Wendroff
+    const R wr = SCH == SCH_LW ? row(q, -sr) : c;
+    const R wt = SCH == SCH_LW ? col(q, -sc) : c;
+    const R tr = conv_term<SCH, R>(aCr, Kr, c, row(q, sr), row(q, 2 * sr), wr);
+    const R tt = conv_term<SCH, R>(aCt, Kt, c, col(q, sc), col(q, 2 * sc), wt);
+    return (R)((rel - (double)tr) - (double)tt);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Combined-scheme update of one node (Eq. combined_scheme): centre values fc,
 // radial neighbours row(q, di) at rows i+di (di = -2, -1, 1, 2; ghost rows
@@ -432,21 +454,8 @@ PCLB_HD inline void node_update_put(const Tables& T, int i, int j, const R* fc, 
       courant<R>((R)speed(k), atr[d4], aCt, Kt);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int d = d4 + 4 * h;
-        const int q = qidx(k, d);
-        const int sr = ((G.rback >> d) & 1u) ? -1 : 1;   // upwind offset in r
-        const int sc = ((G.tback >> d) & 1u) ? -1 : 1;   // upwind offset in theta
-        if constexpr (SCH == SCH_MWB) {
-          put(q, mwb_update<R>(rel[h], fc[q], aCr, Kr, row(q, sr), row(q, 2 * sr), aCt, Kt,
-                               col(q, sc), col(q, 2 * sc)));
-        } else {
-          // the downwind neighbours only matter to Lax-Wendroff
-          const R wr = SCH == SCH_LW ? row(q, -sr) : fc[q];
-          const R wt = SCH == SCH_LW ? col(q, -sc) : fc[q];
-          const R tr = conv_term<SCH, R>(aCr, Kr, fc[q], row(q, sr), row(q, 2 * sr), wr);
-          const R tt = conv_term<SCH, R>(aCt, Kt, fc[q], col(q, sc), col(q, 2 * sc), wt);
-          put(q, (R)((rel[h] - (double)tr) - (double)tt));
-        }
+        const int q = qidx(k, d4 + 4 * h);
+        put(q, velocity_update<R, SCH>(G, d4 + 4 * h, q, rel[h], fc[q], aCr, Kr, aCt, Kt, row, col));
       }
     });
   }

@@ -179,6 +179,34 @@ def richtmyer_meshkov(nr=2048, nth=4096, steps=5000, tau=2e-5, amps=None, seed=1
     return P, dict(rho=rho, ur=ur, ut=0.0 * one, T=T)
 
 
+def rm_sector(light_to_heavy=True, nr=1000, nth=450, steps=20000, shock_r=1.17, A0=0.02,
+              R=1.2, k=20.0, tau=1e-5, dt=1e-5):
+    """The paper's own Richtmyer-Meshkov runs (Sec. III.C): one eighth of the
+    annulus R1 = 1 <= r <= R2 = 2 (N_f = 1), a shock of speed 2 moving outward
+    from the light medium (rho, u_r, P) = (1, 0, 1) into the interface
+    r = R + A0 cos(k R theta) (R = 1.2, A0 = 0.02, k = 20: three wavelengths
+    on the sector), beyond which the medium has rho = 3 (light to heavy) or
+    0.5 (heavy to light) at P = 1.  Behind the shock, inside r = shock_r (a
+    reading: the paper does not place it), the Hugoniot state (1.5, 0.666667,
+    0, P = 2.33333), which the inner boundary keeps supplying.  tau = dt =
+    1e-5 on 1000 x 450 nodes.  P = rho T (gamma = 2)."""
+    r1, r2 = 1.0, 2.0
+    rho_out = 3.0 if light_to_heavy else 0.5
+    rhoH, uH, PH = hugoniot(1.0, 0.0, 1.0, 2.0)
+    P = Problem("rm_sector", nr, nth, r1, r2, tau, dt, steps, (INFLOW, WALL),
+                ((rhoH, uH, 0.0, PH / rhoH), (0, 0, 0, 0)),
+                {"light_to_heavy": light_to_heavy, "A0": A0, "R": R, "k": k,
+                 "shock_r": shock_r, "shock_speed": 2.0}, 1)
+    Rr, TH = node_coords(nr, nth, r1, r2, 1)
+    rI = R + A0 * np.cos(k * R * TH)
+    shocked = Rr < shock_r
+    outer = Rr >= rI
+    rho = np.where(shocked, rhoH, np.where(outer, rho_out, 1.0))
+    T = np.where(shocked, PH / rhoH, np.where(outer, 1.0 / rho_out, 1.0))
+    ur = np.where(shocked, uH, 0.0)
+    return P, dict(rho=rho, ur=ur, ut=np.zeros_like(Rr), T=T)
+
+
 def kelvin_helmholtz(nr=4096, nth=8192, steps=1000, tau=1e-5, warmup=50, cfl=None,
                      tau_equals_dt=False):
     """u_theta = 0.5 tanh((r-1)/0.01), u_r = 1e-3 sin(8 theta) exp(-((r-1)/0.02)^2),
