@@ -149,6 +149,26 @@ def couette_errors(W, Sim, torch):
     return out
 
 
+def rm_sector_runs(W, Sim):
+    """Sec. III.C: the paper's two Richtmyer-Meshkov runs (1000 x 450, one
+    eighth of the annulus, FP64) with the interface followed by markers;
+    the compression ratio, the inversion and recovery times."""
+    from paper_1302_7104_amd import interface as I
+    out = {}
+    for name, lth, t_end in (("light_to_heavy", True, 0.17), ("heavy_to_light", False, 0.32)):
+        P, F = W.rm_sector(light_to_heavy=lth)
+        sim = Sim(P, precision=64)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        t, amp, sgn, _ = I.track_amplitude(sim, P, every=20, t_end=t_end)
+        sim.close()
+        p = P.params
+        c = I.compression(t, amp, sgn, p["A0"], p["R"], p["shock_r"], p["shock_speed"])
+        c["paper"] = {"ratio": 0.715, "theory": 0.758, "t_reco": 0.13} if lth else \
+            {"ratio": 0.65, "theory": 0.61, "t_zero": 0.27, "t_reco": 0.66}
+        out[name] = c
+    return out
+
+
 def adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, precision):
     """J = sum over 1.1 < r < 1.5 of rho^2 r dr dtheta after `steps` steps of
     the Richtmyer-Meshkov recipe, and dJ/da_k through the hand-written
@@ -465,8 +485,8 @@ def main():
     ap.add_argument("--accuracy-only", action="store_true",
                     help="FP32 error against FP64 after the full run of every configuration")
     ap.add_argument("--variants-only", action="store_true",
-                    help="step time per convection scheme, the non-equilibrium fields kernel and "
-                         "the Couette errors, then exit")
+                    help="step time per convection scheme, the non-equilibrium fields kernel, "
+                         "the Couette errors and the sector Richtmyer-Meshkov runs, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -509,6 +529,7 @@ def main():
         print(json.dumps({"schemes_and_noneq_kh4096x8192_fp32": run_variants(W, Sim, torch)}),
               flush=True)
         print(json.dumps({"couette_sector_steady_error": couette_errors(W, Sim, torch)}), flush=True)
+        print(json.dumps({"rm_sector_compression": rm_sector_runs(W, Sim)}), flush=True)
         return
     P, ms, diag = run_forward(W, Sim, torch, 32, args.steps, args.warmup)
     if args.calibrate_copy:
@@ -549,6 +570,7 @@ def main():
                                                  for name in ACCURACY_RUNS}
         extra["schemes_and_noneq_kh4096x8192_fp32"] = run_variants(W, Sim, torch)
         extra["couette_sector_steady_error"] = couette_errors(W, Sim, torch)
+        extra["rm_sector_compression"] = rm_sector_runs(W, Sim)
     out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)

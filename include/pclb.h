@@ -57,7 +57,12 @@ enum {
 enum {
   PCLB_WALL = 0,         /* p[0] = angular velocity omega: u = (0, omega r) at the ghosts */
   PCLB_INFLOW = 1,       /* p = (rho, u_r, u_theta, T) prescribed at the ghosts */
-  PCLB_EXTRAPOLATE = 2   /* u_r, u_theta extrapolated linearly like rho and T */
+  PCLB_EXTRAPOLATE = 2,  /* u_r, u_theta extrapolated linearly like rho and T */
+  /* Flag to OR into a kind: the ghost layers take f^eq of their state plus
+   * the non-equilibrium part f - f^eq of the row next to the wall, instead of
+   * f^eq alone (the non-equilibrium boundary condition Sec. II.C cites).
+   * pclb_adjoint_step refuses contexts that use it. */
+  PCLB_BC_NONEQ = 16
 };
 
 /* Kernel selection for pclb_step / pclb_step_into.  Both kernels give the
@@ -157,8 +162,12 @@ const char* pclb_last_error(const pclb_ctx* ctx);
  * on which every later call enqueues its work.  Buffer 0 becomes current. */
 int pclb_bind(pclb_ctx* ctx, void* f0, void* f1, void* stream);
 
-/* Set the radial boundary of side 0 (inner, r = R1) or 1 (outer, r = R2).
- * Host-side only; takes effect from the next launch. */
+/* Set the radial boundary of side 0 (inner, r = R1) or 1 (outer, r = R2):
+ * kind is PCLB_WALL, PCLB_INFLOW or PCLB_EXTRAPOLATE, optionally ORed with
+ * PCLB_BC_NONEQ; p as listed with the kinds (ignored for EXTRAPOLATE).
+ * PCLB_EINVAL for an unknown side or kind, a missing or non-finite p, or an
+ * inflow density or temperature <= 0.  Host-side only; takes effect from
+ * the next launch. */
 int pclb_set_bc(pclb_ctx* ctx, int32_t side, int32_t kind, const double p[4]);
 
 /* f = f^eq(rho, u, T) on every node of the current buffer (Eq. feq with the

@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 NQ = 33
 WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
+NONEQ = 16     # flag: ghost layers add the wall row's f - f^eq
 # convection schemes and relaxation forms (Sec. II.B; Sec. III.A, Figs. 5-6)
 SCHEME_MWB, SCHEME_WB, SCHEME_LW, SCHEME_UPWIND2 = 0, 1, 2, 3
 RELAX_ANALYTIC, RELAX_EULER = 0, 1

@@ -408,7 +408,7 @@ template <class T>
 void ghost_macros(const OrGrid& g, int side, double rg1, double rg2, double ct, double st,
                   const T m0[4], const T m1[4], T out1[4], T out2[4]) {
   // m0: row adjacent to the wall, m1: next row inward; each (rho, ux, uy, E).
-  int kind = g.bc_kind[side];
+  int kind = g.bc_kind[side] & 15;     // the NONEQ flag (16) does not change the state
   const double* p = g.bc_par[side];
   T rho1 = 2.0 * m0[0] - m1[0];
   T rho2 = 2.0 * rho1 - m0[0];
@@ -470,7 +470,19 @@ int build_padded(const OrGrid& g, const Geometry& geo, const double* f,
       double fe1[NQ], fe2[NQ];
       feq_all(o1[0], o1[1], o1[2], o1[3], fe1);
       feq_all(o2[0], o2[1], o2[2], o2[3], fe2);
-      for (int q = 0; q < NQ; ++q) { P.at(q, ig1, j) = fe1[q]; P.at(q, ig2, j) = fe2[q]; }
+      // non-equilibrium boundary (flag 16): both ghost layers also take the
+      // wall row's f - f^eq
+      double fneq[NQ] = {0};
+      if (g.bc_kind[side] & 16) {
+        double fw[NQ], few[NQ];
+        for (int q = 0; q < NQ; ++q) fw[q] = f[idx(g, q, i0, j)];
+        feq_all(m0[0], m0[1], m0[2], m0[3], few);
+        for (int q = 0; q < NQ; ++q) fneq[q] = fw[q] - few[q];
+      }
+      for (int q = 0; q < NQ; ++q) {
+        P.at(q, ig1, j) = fe1[q] + fneq[q];
+        P.at(q, ig2, j) = fe2[q] + fneq[q];
+      }
     }
   }
   return bad;
@@ -621,7 +633,13 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
       const double* o = (ii == ig1) ? o1 : o2;
       double F[NK + 1];
       weights(o[3], TABLE1[0], F);
-      return feq_q(o[0], o[1], o[2], o[3], F, q);
+      double v = feq_q(o[0], o[1], o[2], o[3], F, q);
+      if (g.bc_kind[side] & 16) {                    // + f - f^eq of the wall row
+        double Fw[NK + 1];
+        weights(m0[3], TABLE1[0], Fw);
+        v += f[idx(g, q, i0, jj)] - feq_q(m0[0], m0[1], m0[2], m0[3], Fw, q);
+      }
+      return v;
     };
     double m[4];
     mac(i, j, m);
@@ -722,7 +740,8 @@ void or_diagnostics(const OrGrid* gp, const double* f, double* out) {
 int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next, double tie_eps,
                     double* lam_out) {
   const OrGrid& g = *gp;
-  if (g.scheme != 0 || g.terms != 7) return -1;   // the adjoint of the combined MWB step only
+  // the adjoint of the combined MWB step with equilibrium ghosts only
+  if (g.scheme != 0 || g.terms != 7 || (g.bc_kind[0] & 16) || (g.bc_kind[1] & 16)) return -1;
   Geometry geo(g);
   size_t tot = (size_t)NQ * g.nr * g.nth, n = (size_t)g.nr * g.nth;
   std::vector<double> m;

@@ -102,6 +102,7 @@ constexpr int SCH_MWB = 0, SCH_WB = 1, SCH_LW = 2, SCH_UPWIND2 = 3;
 // Radial boundary description as the kernels see it.
 struct BCdev {
   int32_t kind[2];     // PCLB_WALL / PCLB_INFLOW / PCLB_EXTRAPOLATE
+  int32_t neq[2];      // 1: ghosts also take the wall row's f - f^eq
   double p[2][4];
   double rg[2][2];     // radius of ghost layer 0 (next to the wall) and 1, per side
 };
@@ -472,7 +473,9 @@ PCLB_HD inline void node_update(const Tables& T, int i, int j, const R* fc, RowF
 // from the macroscopic state of the wall row (f0) and the next row (f1),
 // extrapolate rho and E linearly and recursively (ghost0 = 2 row0 - row1,
 // ghost1 = 2 ghost0 - row0), set u per boundary kind, and return f^eq of
-// both ghost states in g0 and g1.
+// both ghost states in g0 and g1; with bc.neq the non-equilibrium part
+// f - f^eq of the wall row is added to both (the non-equilibrium boundary
+// condition the paper cites for Sec. II.C), in double, rounded once.
 template <class R>
 PCLB_HD inline void ghost_column(const Tables& T, const BCdev& bc, int side, double ct, double st,
                                  const R* f0, const R* f1, R* g0, R* g1) {
@@ -485,6 +488,18 @@ PCLB_HD inline void ghost_column(const Tables& T, const BCdev& bc, int side, dou
   double prev[4] = {m[0][0], m[0][1], m[0][2], m[0][3]};
   double pprev[4] = {m[1][0], m[1][1], m[1][2], m[1][3]};
   const int kind = bc.kind[side];
+  const bool neq = bc.neq[side] != 0;
+  EqCoef c0;
+  if (neq) {
+    const double ux0 = m[0][1], uy0 = m[0][2];
+    eq_setup(T, m[0][0], ux0, uy0, m[0][3], c0);
+  }
+  // f - f^eq of the wall row, velocity q
+  auto neq0 = [&](int q) -> double {
+    if (!neq) return 0.0;
+    const double fe = q == 0 ? c0.rF[0] * c0.A0 : eq_val(c0, k_of(q), d_of(q));
+    return (double)f0[q] - fe;
+  };
   for (int layer = 0; layer < 2; ++layer) {
     double g[4];
     for (int a = 0; a < 4; ++a) g[a] = 2.0 * prev[a] - pprev[a];
@@ -503,9 +518,9 @@ PCLB_HD inline void ghost_column(const Tables& T, const BCdev& bc, int side, dou
     EqCoef c;
     eq_setup(T, rho, ux, uy, E, c);
     R* out = layer == 0 ? g0 : g1;
-    out[0] = (R)(c.rF[0] * c.A0);
+    out[0] = (R)(c.rF[0] * c.A0 + neq0(0));
     for (int k = 1; k <= NK; ++k)
-      for (int d = 0; d < ND; ++d) out[qidx(k, d)] = (R)eq_val(c, k, d);
+      for (int d = 0; d < ND; ++d) out[qidx(k, d)] = (R)(eq_val(c, k, d) + neq0(qidx(k, d)));
   }
 }
 

@@ -216,6 +216,7 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   T.n_mixed = strip_mixed_count(nth, cfg->n_f);
   for (int s = 0; s < 2; ++s) {
     c->bc.kind[s] = PCLB_WALL;
+    c->bc.neq[s] = 0;
     for (int a = 0; a < 4; ++a) c->bc.p[s][a] = 0.0;
   }
   c->bc.rg[0][0] = cfg->r1 - c->dr;
@@ -256,6 +257,8 @@ int pclb_bind(pclb_ctx* c, void* f0, void* f1, void* stream) {
 int pclb_set_bc(pclb_ctx* c, int32_t side, int32_t kind, const double p[4]) {
   if (!c) return PCLB_EINVAL;
   if (side < 0 || side > 1) return fail(c, PCLB_EINVAL, "side must be 0 (inner) or 1 (outer)");
+  const int neq = (kind & PCLB_BC_NONEQ) ? 1 : 0;
+  kind &= ~PCLB_BC_NONEQ;
   if (kind < PCLB_WALL || kind > PCLB_EXTRAPOLATE) return fail(c, PCLB_EINVAL, "unknown boundary kind");
   double q[4] = {0, 0, 0, 0};
   if (kind != PCLB_EXTRAPOLATE) {
@@ -267,6 +270,7 @@ int pclb_set_bc(pclb_ctx* c, int32_t side, int32_t kind, const double p[4]) {
   if (kind == PCLB_INFLOW && (!(q[0] > 0.0) || !(q[3] > 0.0)))
     return fail(c, PCLB_EINVAL, "inflow density and temperature must be > 0");
   c->bc.kind[side] = kind;
+  c->bc.neq[side] = neq;
   for (int a = 0; a < 4; ++a) c->bc.p[side][a] = q[a];
   return PCLB_OK;
 }
@@ -398,6 +402,8 @@ int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* 
   if (!f_t || !lam_next || !lam_out || lam_out == lam_next || lam_out == f_t)
     return fail(c, PCLB_EINVAL, "three non-null buffers, lam_out distinct from the inputs");
   if (c->cfg.scheme != PCLB_SCHEME_MWB) return fail(c, PCLB_EINVAL, "the adjoint covers the MWB scheme only");
+  if (c->bc.neq[0] || c->bc.neq[1])
+    return fail(c, PCLB_EINVAL, "the adjoint covers equilibrium ghost layers only (no PCLB_BC_NONEQ)");
   hipError_t e = c->cfg.precision == 32
                      ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream)
                      : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream);

@@ -74,18 +74,28 @@ def track_amplitude(sim, problem, markers: int = 450, every: int = 20, t_end: fl
     return np.array(ts), np.array(amp), np.array(sgn), np.array(mean)
 
 
-def compression(t, amp, A0, R, shock_r, shock_speed, t_comp=0.03):
+def compression(t, amp, signed, A0, R, shock_r, shock_speed, t_comp=0.03):
     """The quantities the paper reads off its Figs. 8 and 10, with time zero
-    where the incident shock reaches the interface's trough: the amplitude
-    t_comp = 0.03 later (the paper's end of the compression stage in both
-    cases) and its ratio to A0 (the compression ratio), the smallest
-    amplitude in the first 0.1 and when it occurs, and the first time the
-    amplitude is back at A0 after that minimum (None if not within the run)."""
+    where the incident shock reaches the interface's trough:
+      ratio      the amplitude t_comp = 0.03 later (the paper's end of the
+                 compression stage in both runs) over A0: the compression ratio;
+      A_min, t_min  the smallest amplitude in the first 0.1 and its time;
+      t_zero     the first time the signed amplitude changes sign (the
+                 interface inverts; heavy to light), or None;
+      t_reco     the first time after t_min and t_zero at which the amplitude
+                 is back at A0, or None within the run."""
     t0 = (R - A0 - shock_r) / shock_speed
     a_tc = float(np.interp(t0 + t_comp, t, amp))
     sel = (t >= t0) & (t <= t0 + 0.1)
     k = int(np.argmin(np.where(sel, amp, np.inf)))
-    after = np.nonzero((t > t[k]) & (amp >= A0))[0]
+    flips = np.nonzero((t > t0) & (np.sign(signed) != np.sign(signed[0])))[0]
+    t_zero = None
+    if len(flips):
+        m = flips[0]
+        # linear interpolation of the crossing between the last two samples
+        t_zero = float(t[m - 1] + (t[m] - t[m - 1]) * signed[m - 1] / (signed[m - 1] - signed[m]) - t0)
+    start = max(t[k], t0 + (t_zero if t_zero is not None else 0.0))
+    after = np.nonzero((t > start) & (amp >= A0))[0]
     return {"t_meet": t0, "A_at_t_comp": a_tc, "ratio": a_tc / A0,
-            "A_min": float(amp[k]), "t_min": float(t[k] - t0),
+            "A_min": float(amp[k]), "t_min": float(t[k] - t0), "t_zero": t_zero,
             "t_reco": float(t[after[0]] - t0) if len(after) else None}

@@ -25,8 +25,10 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-# Radial boundary kinds (Sec. II.C, radial boundary condition).
+# Radial boundary kinds (Sec. II.C, radial boundary condition), and the flag
+# that adds the wall row's non-equilibrium part f - f^eq to the ghost layers.
 WALL, INFLOW, EXTRAPOLATE = 0, 1, 2
+NONEQ = 16
 
 #: Courant number of the time-step rule, per recipe (see cfl_dt).  The
 #: configurations ask for 0.3 throughout.  The combined scheme (relaxation and
@@ -188,12 +190,16 @@ def rm_sector(light_to_heavy=True, nr=1000, nth=450, steps=20000, shock_r=1.17, 
     on the sector), beyond which the medium has rho = 3 (light to heavy) or
     0.5 (heavy to light) at P = 1.  Behind the shock, inside r = shock_r (a
     reading: the paper does not place it), the Hugoniot state (1.5, 0.666667,
-    0, P = 2.33333), which the inner boundary keeps supplying.  tau = dt =
-    1e-5 on 1000 x 450 nodes.  P = rho T (gamma = 2)."""
+    0, P = 2.33333), which the inner boundary keeps supplying; the outer
+    boundary extrapolates (a reading: the paper does not state it; a wall
+    there reflects the transmitted shock back onto the interface, and in the
+    heavy-to-light case the reflection breaks the run down before the
+    amplitude recovers).  tau = dt = 1e-5 on 1000 x 450 nodes.  P = rho T
+    (gamma = 2)."""
     r1, r2 = 1.0, 2.0
     rho_out = 3.0 if light_to_heavy else 0.5
     rhoH, uH, PH = hugoniot(1.0, 0.0, 1.0, 2.0)
-    P = Problem("rm_sector", nr, nth, r1, r2, tau, dt, steps, (INFLOW, WALL),
+    P = Problem("rm_sector", nr, nth, r1, r2, tau, dt, steps, (INFLOW, EXTRAPOLATE),
                 ((rhoH, uH, 0.0, PH / rhoH), (0, 0, 0, 0)),
                 {"light_to_heavy": light_to_heavy, "A0": A0, "R": R, "k": k,
                  "shock_r": shock_r, "shock_speed": 2.0}, 1)

@@ -40,7 +40,8 @@ struct Setup {
     T.rinv = rinv.data();
     T.wA = wA.data();
     for (int s = 0; s < 2; ++s) {
-      bc.kind[s] = kind[s];
+      bc.kind[s] = kind[s] & 15;
+      bc.neq[s] = (kind[s] & 16) ? 1 : 0;
       for (int a = 0; a < 4; ++a) bc.p[s][a] = par[4 * s + a];
     }
     bc.rg[0][0] = r1 - dr; bc.rg[0][1] = r1 - 2.0 * dr;

@@ -50,8 +50,13 @@ BCS = [((W.WALL, (0.2, 0, 0, 0)), (W.WALL, (-0.1, 0, 0, 0))),
        ((W.EXTRAPOLATE, (0, 0, 0, 0)), (W.INFLOW, (0.9, -0.03, 0.1, 0.95)))]
 
 
+# the non-equilibrium radial boundary on both sides
+BCS_NEQ = [((W.WALL | W.NONEQ, (0.2, 0, 0, 0)), (W.INFLOW | W.NONEQ, (0.9, -0.03, 0.1, 0.95))),
+           ((W.EXTRAPOLATE | W.NONEQ, (0, 0, 0, 0)), (W.WALL | W.NONEQ, (-0.1, 0, 0, 0)))]
+
+
 @pytest.mark.parametrize("nf", [8, 1, 3])
-@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("bc", BCS + BCS_NEQ)
 def test_emulated_device_step_matches_oracle(emu, bc, nf):
     """nf = 8 is the full annulus; 1 and 3 are sectors whose azimuthal ghosts
     rotate the direction index (Sec. II.C)."""

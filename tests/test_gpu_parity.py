@@ -88,6 +88,27 @@ def test_step_parity_fp64_small(bc, kernel):
     assert rel(got, want) <= FP64_TOL, rel(got, want)
 
 
+BCS_NEQ = [((W.WALL | W.NONEQ, (0.2, 0, 0, 0)), (W.INFLOW | W.NONEQ, (0.9, -0.03, 0.1, 0.95))),
+           ((W.EXTRAPOLATE | W.NONEQ, (0, 0, 0, 0)), (W.WALL | W.NONEQ, (-0.1, 0, 0, 0)))]
+
+
+@pytest.mark.parametrize("bc", BCS_NEQ)
+@pytest.mark.parametrize("kernel", [1, 0])
+def test_step_parity_noneq_boundary(bc, kernel):
+    """The non-equilibrium radial boundary (ghosts = f^eq of their state plus
+    the wall row's f - f^eq): FP64 within 1e-12 of the oracle, FP32 within
+    2e-7, on both kernels."""
+    P, F = smooth_problem(37, 250, bc, 6)
+    for prec, tol in ((64, FP64_TOL), (32, 2e-7)):
+        s, f0 = start(P, F, prec, noise_seed=7, kernel=kernel)
+        s.step(5)
+        got = s.state.double().cpu().numpy()
+        want, bad = O.step(grid_of(P), f0, 5)
+        assert bad == 0
+        assert rel(got, want) <= tol, (prec, rel(got, want))
+        s.close()
+
+
 @pytest.mark.parametrize("bc", BCS)
 def test_step_parity_fp32_small(bc):
     P, F = smooth_problem(37, 250, bc, 4)

@@ -743,3 +743,54 @@ def test_combined_step_is_sum_of_separate_terms():
     # each part does something on this state
     for part in (rel_only - f0, r_only - f0, t_only - f0):
         assert np.abs(part).max() > 1e-6 * np.abs(f0).max()
+
+
+# --------------------------------------------------------------------------
+# Non-equilibrium radial boundary (flag NONEQ): ghost = f^eq(ghost state) +
+# (f - f^eq) of the wall row.
+
+def test_noneq_boundary_equals_equilibrium_boundary_at_equilibrium():
+    """With f = f^eq everywhere the non-equilibrium part of the wall rows is
+    zero (to rounding), so the flag changes nothing."""
+    P, F = W.smooth_random(9, 24, seed=41, amp=0.05, bc=(W.WALL, W.INFLOW),
+                           bc_par=((0.1, 0, 0, 0), (1.05, 0.02, 0.01, 1.02)))
+    g = grid_of(P)
+    f0 = O.init_feq(g, **F)
+    gn = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, (W.WALL | W.NONEQ, W.INFLOW | W.NONEQ),
+                P.bc_par, nf=P.nf)
+    a, _ = O.step(g, f0, 1)
+    b, _ = O.step(gn, f0, 1)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+def test_noneq_boundary_keeps_a_uniform_nonequilibrium_state_uniform():
+    """A spatially uniform state off equilibrium with extrapolating radial
+    boundaries: with the flag the ghosts repeat the wall rows exactly, every
+    upwind difference vanishes, and one step is the relaxation alone at
+    every node; without it the ghosts are f^eq and the wall rows move."""
+    nr, nth = 8, 16
+    P, F = W.uniform(nr, nth, rho=1.1, ux=0.2, uy=-0.1, T=0.9, tau=2e-3,
+                     bc=(W.EXTRAPOLATE, W.EXTRAPOLATE))
+    g = grid_of(P)
+    feq = O.init_feq(g, **F)
+    # the same non-equilibrium perturbation (in the Cartesian frame) at
+    # every node: a function of the velocity index only
+    pert = W.noise((33, 1, 1), 5e-3, 42)
+    f0 = feq[:, :1, :1] * (1.0 + pert) * np.ones((33, nr, nth))
+    gn = O.Grid(nr, nth, P.r1, P.r2, P.tau, P.dt, (W.EXTRAPOLATE | W.NONEQ, W.EXTRAPOLATE | W.NONEQ),
+                P.bc_par, nf=P.nf)
+    out, _ = O.step(gn, f0, 1)
+    relax_only = O.Grid(nr, nth, P.r1, P.r2, P.tau, P.dt, gn.bc_kind, P.bc_par, terms=1, nf=P.nf)
+    want, _ = O.step(relax_only, f0, 1)
+    assert np.abs(out - want).max() <= 1e-14 * np.abs(want).max()
+    plain, _ = O.step(g, f0, 1)
+    assert np.abs(plain - want).max() > 1e-6 * np.abs(want).max()
+
+
+def test_adjoint_refuses_noneq_boundary():
+    P, F = W.smooth_random(6, 16, seed=43, bc=(W.EXTRAPOLATE, W.EXTRAPOLATE))
+    gn = O.Grid(P.nr, P.nth, P.r1, P.r2, P.tau, P.dt, (W.EXTRAPOLATE | W.NONEQ, W.EXTRAPOLATE),
+                P.bc_par, nf=P.nf)
+    f0 = O.init_feq(gn, **F)
+    with pytest.raises(ValueError):
+        O.adjoint_step(gn, f0, f0)
