@@ -49,7 +49,8 @@ class _OrGrid(ctypes.Structure):
                 ("bc_kind", ctypes.c_int32 * 2),
                 ("bc_par", (ctypes.c_double * 4) * 2),
                 ("terms", ctypes.c_int32), ("nf", ctypes.c_int32),
-                ("scheme", ctypes.c_int32), ("relax", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("relax", ctypes.c_int32),
+                ("ni", ctypes.c_int32)]
 
 
 @dataclass
@@ -68,10 +69,17 @@ class Grid:
     nf: int = 8           # theta covers 2 pi nf / 8 (Sec. II.C); 8 = full annulus
     scheme: int = 0       # SCHEME_MWB, SCHEME_WB, SCHEME_LW, SCHEME_UPWIND2
     relax: int = 0        # RELAX_ANALYTIC (Eq. operator1_new), RELAX_EULER (Eq. operator1_old)
+    ni: int = 8           # directions per speed: 8, 16, 24 (Table I); nf counts in units of 2 pi / ni
+
+    @property
+    def nq(self) -> int:
+        return 1 + 4 * int(self.ni)
 
     def c(self) -> _OrGrid:
-        if not 1 <= int(self.nf) <= 8:
-            raise ValueError("nf must be in 1..8")
+        if int(self.ni) not in (8, 16, 24):
+            raise ValueError("ni must be 8, 16 or 24")
+        if not 1 <= int(self.nf) <= int(self.ni):
+            raise ValueError("nf must be in 1..ni")
         g = _OrGrid()
         g.nr, g.nth = self.nr, self.nth
         g.r1, g.r2, g.tau, g.dt = self.r1, self.r2, self.tau, self.dt
@@ -84,6 +92,7 @@ class Grid:
         g.nf = int(self.nf)
         g.scheme = int(self.scheme)
         g.relax = int(self.relax)
+        g.ni = int(self.ni)
         return g
 
 
@@ -207,7 +216,7 @@ def mwb_grad(C, psi5, tie_eps: float = TIE_FP64) -> np.ndarray:
 def step(grid: Grid, f: np.ndarray, nsteps: int) -> tuple[np.ndarray, int]:
     """Eq. combined_scheme applied ``nsteps`` times.  Returns (f, bad_ghosts)."""
     f = _f64(f)
-    assert f.shape == (NQ, grid.nr, grid.nth)
+    assert f.shape == (grid.nq, grid.nr, grid.nth)
     out = np.empty_like(f)
     g = grid.c()
     bad = lib().or_step(ctypes.byref(g), _p(f), _p(out), int(nsteps))
@@ -218,9 +227,9 @@ def step_sample(grid: Grid, f: np.ndarray, nodes) -> np.ndarray:
     """One step of Eq. combined_scheme at the listed (i, j) nodes only;
     returns (len(nodes), 33).  ``f`` may be float32 or float64 (converted)."""
     f = _f64(f)
-    assert f.shape == (NQ, grid.nr, grid.nth)
+    assert f.shape == (grid.nq, grid.nr, grid.nth)
     nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.int32).reshape(-1, 2))
-    out = np.empty((len(nd), NQ))
+    out = np.empty((len(nd), grid.nq))
     g = grid.c()
     lib().or_step_sample(ctypes.byref(g), _p(f), nd.ctypes.data_as(_I), len(nd), _p(out))
     return out
@@ -228,7 +237,7 @@ def step_sample(grid: Grid, f: np.ndarray, nodes) -> np.ndarray:
 
 def init_feq(grid: Grid, rho, ur, ut, T) -> np.ndarray:
     rho, ur, ut, T = (_f64(a) for a in (rho, ur, ut, T))
-    f = np.empty((NQ, grid.nr, grid.nth))
+    f = np.empty((grid.nq, grid.nr, grid.nth))
     g = grid.c()
     lib().or_init_feq(ctypes.byref(g), _p(rho), _p(ur), _p(ut), _p(T), _p(f))
     return f

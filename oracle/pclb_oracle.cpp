@@ -49,7 +49,8 @@ namespace {
 
 constexpr int NK = 4;             // non-zero speed groups (Sec. II.A)
 constexpr int NI = 8;             // directions per group, octagon model
-constexpr int NQ = 1 + NK * NI;   // 33 discrete velocities
+constexpr int NQ = 1 + NK * NI;   // 33 discrete velocities of the octagon
+constexpr int NQ_MAX = 1 + NK * 24;   // 97: the triple octagon
 constexpr double PI = 3.14159265358979323846;
 
 // Speeds v_0..v_4 (Sec. II.A, after Eq. DVM1).
@@ -63,23 +64,31 @@ const TableRow TABLE1[3] = {
     {24, 24.0, -1.0 / 12.0, 1.0 / 3.0, -2.0, 16.0},
 };
 
-// Eq. DVM1: v_kix = v_k cos[2 pi (i-1)/N_i], v_kiy = v_k sin[...].
+// Eq. DVM1 for N_i directions per speed (8 octagon, 16 double, 24 triple
+// octagon): v_kix = v_k cos[2 pi (i-1)/N_i], v_kiy = v_k sin[...];
+// q = 1 + N_i (k-1) + (i-1), q = 0 the rest velocity.
 struct Velocities {
-  double vx[NQ], vy[NQ];
-  int k[NQ];
-  Velocities() {
+  int ni, nq;
+  double vx[NQ_MAX], vy[NQ_MAX];
+  int k[NQ_MAX];
+  explicit Velocities(int n) : ni(n), nq(1 + NK * n) {
     vx[0] = 0.0; vy[0] = 0.0; k[0] = 0;
     for (int kk = 1; kk <= NK; ++kk)
-      for (int i = 1; i <= NI; ++i) {
-        int q = 1 + NI * (kk - 1) + (i - 1);
-        double phi = 2.0 * PI * (i - 1) / NI;
+      for (int i = 1; i <= ni; ++i) {
+        int q = 1 + ni * (kk - 1) + (i - 1);
+        double phi = 2.0 * PI * (i - 1) / ni;
         vx[q] = VK[kk] * std::cos(phi);
         vy[q] = VK[kk] * std::sin(phi);
         k[q] = kk;
       }
   }
 };
-const Velocities V;
+const Velocities VELS[3] = {Velocities(8), Velocities(16), Velocities(24)};
+// the model of a grid (its N_i) and its Table I row
+inline const Velocities& vel_of(int ni) { return ni == 24 ? VELS[2] : ni == 16 ? VELS[1] : VELS[0]; }
+inline const TableRow& row_of(int ni) { return ni == 24 ? TABLE1[2] : ni == 16 ? TABLE1[1] : TABLE1[0]; }
+// the octagon, for the node-level helpers that take no grid
+const Velocities& V = VELS[0];
 
 // ---------------------------------------------------------------------------
 // Forward-mode dual numbers, used only to differentiate the equilibrium and
@@ -144,11 +153,13 @@ template <class T> void weights(const T& E, const TableRow& tb, T F[NK + 1]) {
   F[0] = 1.0 - tb.b0 * sum;
 }
 
-// Eq. feq: the polynomial equilibrium of velocity q for (rho, u, E).
+// Eq. feq: the polynomial equilibrium of velocity q of the set W for
+// (rho, u, E), with the weights F of W's Table I row.
 template <class T>
-T feq_q(const T& rho, const T& ux, const T& uy, const T& E, const T F[NK + 1], int q) {
+T feq_q(const Velocities& W, const T& rho, const T& ux, const T& uy, const T& E,
+        const T F[NK + 1], int q) {
   T u2 = ux * ux + uy * uy;
-  T w = V.vx[q] * ux + V.vy[q] * uy;          // v_ki . u
+  T w = W.vx[q] * ux + W.vy[q] * uy;          // v_ki . u
   T one_m = 1.0 - u2 / (2.0 * E);             // (1 - u^2 / 2E)
   T E2 = E * E;
   T br = (1.0 - u2 / (2.0 * E) + (u2 * u2) / (8.0 * E2))
@@ -156,28 +167,39 @@ T feq_q(const T& rho, const T& ux, const T& uy, const T& E, const T F[NK + 1], i
        + ((w * w) / (2.0 * E2)) * one_m
        + (w * w * w) / (6.0 * E2 * E)
        + (w * w * w * w) / (24.0 * E2 * E2);
-  return rho * F[V.k[q]] * br;
+  return rho * F[W.k[q]] * br;
+}
+template <class T>
+T feq_q(const T& rho, const T& ux, const T& uy, const T& E, const T F[NK + 1], int q) {
+  return feq_q(V, rho, ux, uy, E, F, q);
 }
 
 template <class T>
-void feq_all(const T& rho, const T& ux, const T& uy, const T& E, T out[NQ]) {
+void feq_all(const Velocities& W, const T& rho, const T& ux, const T& uy, const T& E, T* out) {
   T F[NK + 1];
-  weights(E, TABLE1[0], F);
-  for (int q = 0; q < NQ; ++q) out[q] = feq_q(rho, ux, uy, E, F, q);
+  weights(E, row_of(W.ni), F);
+  for (int q = 0; q < W.nq; ++q) out[q] = feq_q(W, rho, ux, uy, E, F, q);
+}
+template <class T>
+void feq_all(const T& rho, const T& ux, const T& uy, const T& E, T* out) {
+  feq_all(V, rho, ux, uy, E, out);
 }
 
 // Eqs. moment1-moment3: rho = sum f, rho u = sum f v,
-// rho E = sum (1/2) f (v - u).(v - u).
-void macros(const double f[NQ], double& rho, double& ux, double& uy, double& E) {
+// rho E = sum (1/2) f (v - u).(v - u), over the velocity set W.
+void macros(const Velocities& W, const double* f, double& rho, double& ux, double& uy, double& E) {
   rho = 0; double jx = 0, jy = 0;
-  for (int q = 0; q < NQ; ++q) { rho += f[q]; jx += f[q] * V.vx[q]; jy += f[q] * V.vy[q]; }
+  for (int q = 0; q < W.nq; ++q) { rho += f[q]; jx += f[q] * W.vx[q]; jy += f[q] * W.vy[q]; }
   ux = jx / rho; uy = jy / rho;
   double e2 = 0;
-  for (int q = 0; q < NQ; ++q) {
-    double cx = V.vx[q] - ux, cy = V.vy[q] - uy;
+  for (int q = 0; q < W.nq; ++q) {
+    double cx = W.vx[q] - ux, cy = W.vy[q] - uy;
     e2 += 0.5 * f[q] * (cx * cx + cy * cy);
   }
   E = e2 / rho;
+}
+void macros(const double* f, double& rho, double& ux, double& uy, double& E) {
+  macros(V, f, rho, ux, uy, E);
 }
 
 // The same macroscopic fields written as a function of the four linear
@@ -317,6 +339,7 @@ struct OrGrid {
   int32_t scheme;  // convection: 0 MWB (Eq. MWB Scheme), 1 Warming-Beam (Eq. WB_Scheme_1),
                    // 2 Lax-Wendroff, 3 second-order upwind (Sec. II.B, Sec. III.A Figs. 5-6)
   int32_t relax;   // relaxation: 0 analytic (Eq. operator1_new), 1 forward Euler (Eq. operator1_old)
+  int32_t ni;      // N_i: 8 octagon, 16 double, 24 triple octagon (Table I); 1 + 4 N_i velocities
 };
 
 namespace {
@@ -327,7 +350,7 @@ struct Geometry {
   std::vector<double> r, ct, st;
   explicit Geometry(const OrGrid& g) : nr(g.nr), nth(g.nth) {
     dr = (g.r2 - g.r1) / (nr - 1);
-    dth = 2.0 * PI * g.nf / (NI * (double)nth);     // Sec. II.C: 2 pi N_f / (N_i N_theta)
+    dth = 2.0 * PI * g.nf / (g.ni * (double)nth);   // Sec. II.C: 2 pi N_f / (N_i N_theta)
     r.resize(nr + 4);                      // r of rows -2..nr+1
     for (int i = -2; i < nr + 2; ++i) r[i + 2] = g.r1 + i * dr;
     ct.resize(nth); st.resize(nth);
@@ -343,8 +366,8 @@ struct Geometry {
 struct Padded {
   int nr, nth, W, H;
   std::vector<double> a;
-  Padded(int nr_, int nth_) : nr(nr_), nth(nth_), W(nth_ + 4), H(nr_ + 4),
-                              a((size_t)NQ * (nr_ + 4) * (nth_ + 4), 0.0) {}
+  Padded(int nr_, int nth_, int nq) : nr(nr_), nth(nth_), W(nth_ + 4), H(nr_ + 4),
+                                      a((size_t)nq * (nr_ + 4) * (nth_ + 4), 0.0) {}
   double& at(int q, int i, int j) { return a[((size_t)q * H + (i + 2)) * W + (j + 2)]; }
   double at(int q, int i, int j) const { return a[((size_t)q * H + (i + 2)) * W + (j + 2)]; }
 };
@@ -370,32 +393,34 @@ inline int paper_mod(int a, int b) { return a <= b ? a : a - b; }
 // i = 1..N_i is the paper's direction index, q = 1 + N_i (k - 1) + (i - 1).
 // Sets the real column and the velocity read there.
 void azimuthal_source(const OrGrid& g, int q, int jv, int& q_src, int& j_src) {
+  const Velocities& VG = vel_of(g.ni);
   q_src = q;
   j_src = jv;
   if (jv >= 0 && jv < g.nth) return;
-  int i_dir = q == 0 ? 0 : (q - 1) % NI + 1;
+  int i_dir = q == 0 ? 0 : (q - 1) % VG.ni + 1;
   int i_src = i_dir;
   if (jv < 0) {
     j_src = jv + g.nth;
-    if (q != 0) i_src = paper_mod(i_dir + g.nf, NI);
+    if (q != 0) i_src = paper_mod(i_dir + g.nf, VG.ni);
   } else {
     j_src = jv - g.nth;
-    if (q != 0) i_src = paper_mod(i_dir - g.nf + NI, NI);
+    if (q != 0) i_src = paper_mod(i_dir - g.nf + VG.ni, VG.ni);
   }
   if (q != 0) q_src = q - i_dir + i_src;
 }
 
 // Macroscopic fields (rho, u_x, u_y, E) of every real node.
 void all_macros(const OrGrid& g, const double* f, std::vector<double>& m) {
+  const Velocities& VG = vel_of(g.ni);
   m.assign((size_t)4 * g.nr * g.nth, 0.0);
   size_t n = (size_t)g.nr * g.nth;
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < g.nr; ++i)
     for (int j = 0; j < g.nth; ++j) {
-      double fl[NQ];
-      for (int q = 0; q < NQ; ++q) fl[q] = f[idx(g, q, i, j)];
+      double fl[NQ_MAX];
+      for (int q = 0; q < VG.nq; ++q) fl[q] = f[idx(g, q, i, j)];
       size_t c = (size_t)i * g.nth + j;
-      macros(fl, m[c], m[n + c], m[2 * n + c], m[3 * n + c]);
+      macros(VG, fl, m[c], m[n + c], m[2 * n + c], m[3 * n + c]);
     }
 }
 
@@ -439,13 +464,14 @@ void ghost_macros(const OrGrid& g, int side, double rg1, double rg2, double ct, 
 // extrapolated rho or T is not positive.
 int build_padded(const OrGrid& g, const Geometry& geo, const double* f,
                  const std::vector<double>& m, Padded& P) {
+  const Velocities& VG = vel_of(g.ni);
 #pragma omp parallel for schedule(static)
-  for (int q = 0; q < NQ; ++q)
+  for (int q = 0; q < VG.nq; ++q)
     for (int i = 0; i < g.nr; ++i)
       for (int j = 0; j < g.nth; ++j) P.at(q, i, j) = f[idx(g, q, i, j)];
   // azimuthal ghosts: i_theta <= 0 takes i_theta + N_theta, i_theta > N_theta
   // takes i_theta - N_theta, each with its rotated direction index
-  for (int q = 0; q < NQ; ++q)
+  for (int q = 0; q < VG.nq; ++q)
     for (int i = 0; i < g.nr; ++i)
       for (int jv : {-2, -1, g.nth, g.nth + 1}) {
         int qs, js;
@@ -467,19 +493,19 @@ int build_padded(const OrGrid& g, const Geometry& geo, const double* f,
       }
       ghost_macros<double>(g, side, geo.rr(ig1), geo.rr(ig2), geo.ct[j], geo.st[j], m0, m1, o1, o2);
       if (!(o1[0] > 0) || !(o1[3] > 0) || !(o2[0] > 0) || !(o2[3] > 0)) ++bad;
-      double fe1[NQ], fe2[NQ];
-      feq_all(o1[0], o1[1], o1[2], o1[3], fe1);
-      feq_all(o2[0], o2[1], o2[2], o2[3], fe2);
+      double fe1[NQ_MAX], fe2[NQ_MAX];
+      feq_all(VG, o1[0], o1[1], o1[2], o1[3], fe1);
+      feq_all(VG, o2[0], o2[1], o2[2], o2[3], fe2);
       // non-equilibrium boundary (flag 16): both ghost layers also take the
       // wall row's f - f^eq
-      double fneq[NQ] = {0};
+      double fneq[NQ_MAX] = {0};
       if (g.bc_kind[side] & 16) {
-        double fw[NQ], few[NQ];
-        for (int q = 0; q < NQ; ++q) fw[q] = f[idx(g, q, i0, j)];
-        feq_all(m0[0], m0[1], m0[2], m0[3], few);
-        for (int q = 0; q < NQ; ++q) fneq[q] = fw[q] - few[q];
+        double fw[NQ_MAX], few[NQ_MAX];
+        for (int q = 0; q < VG.nq; ++q) fw[q] = f[idx(g, q, i0, j)];
+        feq_all(VG, m0[0], m0[1], m0[2], m0[3], few);
+        for (int q = 0; q < VG.nq; ++q) fneq[q] = fw[q] - few[q];
       }
-      for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < VG.nq; ++q) {
         P.at(q, ig1, j) = fe1[q] + fneq[q];
         P.at(q, ig2, j) = fe2[q] + fneq[q];
       }
@@ -488,8 +514,8 @@ int build_padded(const OrGrid& g, const Geometry& geo, const double* f,
   return bad;
 }
 
-inline double vr_of(int q, double ct, double st) { return V.vx[q] * ct + V.vy[q] * st; }
-inline double vt_of(int q, double ct, double st) { return -V.vx[q] * st + V.vy[q] * ct; }
+inline double vr_of(const Velocities& W, int q, double ct, double st) { return W.vx[q] * ct + W.vy[q] * st; }
+inline double vt_of(const Velocities& W, int q, double ct, double st) { return -W.vx[q] * st + W.vy[q] * ct; }
 
 }  // namespace
 
@@ -549,10 +575,11 @@ void or_mwb_grad(double C, const double* psi, double tie_eps, double* g) {
 // non-positive extrapolated density or temperature (0 in a healthy run).
 int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
-  size_t tot = (size_t)NQ * g.nr * g.nth;
+  size_t tot = (size_t)VG.nq * g.nr * g.nth;
   std::vector<double> cur(f_in, f_in + tot), m;
-  Padded P(g.nr, g.nth);
+  Padded P(g.nr, g.nth, VG.nq);
   int bad = 0;
   for (int s = 0; s < nsteps; ++s) {
     all_macros(g, cur.data(), m);                 // moments of every real node
@@ -563,15 +590,15 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
       double r = geo.rr(i);
       for (int j = 0; j < g.nth; ++j) {
         size_t c = (size_t)i * g.nth + j;
-        double fe[NQ];
-        feq_all(m[c], m[n + c], m[2 * n + c], m[3 * n + c], fe);
-        for (int q = 0; q < NQ; ++q) {
+        double fe[NQ_MAX];
+        feq_all(VG, m[c], m[n + c], m[2 * n + c], m[3 * n + c], fe);
+        for (int q = 0; q < VG.nq; ++q) {
           double ft = P.at(q, i, j);
           double out = 0.0;
           if (g.terms & 1) out += relax_value(g, ft, fe[q]);   // Eqs. operator1_new / _old
           else out += ft;
-          double Cr = vr_of(q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
-          double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
+          double Cr = vr_of(VG, q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
+          double Ct = vt_of(VG, q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
           if (g.terms & 2) {
             double psi[5] = {P.at(q, i - 2, j), P.at(q, i - 1, j), ft, P.at(q, i + 1, j), P.at(q, i + 2, j)};
             out -= convection_term(g.scheme, Cr, psi);
@@ -585,7 +612,7 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
       }
     }
 #pragma omp parallel for schedule(static)
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < VG.nq; ++q) {
       const size_t b = (size_t)q * g.nr * g.nth, e = b + (size_t)g.nr * g.nth;
       std::copy(f_out + b, f_out + e, cur.begin() + b);
     }
@@ -601,18 +628,19 @@ int or_step(const OrGrid* gp, const double* f_in, double* f_out, int32_t nsteps)
 void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int32_t count,
                     double* out) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
 #pragma omp parallel for schedule(dynamic)
   for (int n = 0; n < count; ++n) {
     const int i = nodes[2 * n], j = nodes[2 * n + 1];
-    auto node_f = [&](int ii, int jj, double fl[NQ]) {
-      for (int q = 0; q < NQ; ++q) fl[q] = f[idx(g, q, ii, jj)];
+    auto node_f = [&](int ii, int jj, double fl[NQ_MAX]) {
+      for (int q = 0; q < VG.nq; ++q) fl[q] = f[idx(g, q, ii, jj)];
     };
     // macroscopic fields of any real node
     auto mac = [&](int ii, int jj, double m[4]) {
-      double fl[NQ];
+      double fl[NQ_MAX];
       node_f(ii, jj, fl);
-      macros(fl, m[0], m[1], m[2], m[3]);
+      macros(VG, fl, m[0], m[1], m[2], m[3]);
     };
     // f_q at row ii (possibly a ghost row) of a real column jj, or at a real
     // row ii of a column up to two places beyond the ends (azimuthal ghosts)
@@ -632,25 +660,25 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
       ghost_macros<double>(g, side, geo.rr(ig1), geo.rr(ig2), geo.ct[jj], geo.st[jj], m0, m1, o1, o2);
       const double* o = (ii == ig1) ? o1 : o2;
       double F[NK + 1];
-      weights(o[3], TABLE1[0], F);
-      double v = feq_q(o[0], o[1], o[2], o[3], F, q);
+      weights(o[3], row_of(g.ni), F);
+      double v = feq_q(VG, o[0], o[1], o[2], o[3], F, q);
       if (g.bc_kind[side] & 16) {                    // + f - f^eq of the wall row
         double Fw[NK + 1];
-        weights(m0[3], TABLE1[0], Fw);
-        v += f[idx(g, q, i0, jj)] - feq_q(m0[0], m0[1], m0[2], m0[3], Fw, q);
+        weights(m0[3], row_of(g.ni), Fw);
+        v += f[idx(g, q, i0, jj)] - feq_q(VG, m0[0], m0[1], m0[2], m0[3], Fw, q);
       }
       return v;
     };
     double m[4];
     mac(i, j, m);
-    double fe[NQ];
-    feq_all(m[0], m[1], m[2], m[3], fe);
+    double fe[NQ_MAX];
+    feq_all(VG, m[0], m[1], m[2], m[3], fe);
     double r = geo.rr(i);
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < VG.nq; ++q) {
       double ft = f[idx(g, q, i, j)];
       double res = relax_value(g, ft, fe[q]);
-      double Cr = vr_of(q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
-      double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
+      double Cr = vr_of(VG, q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
+      double Ct = vt_of(VG, q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
       double pr[5], pt[5];
       for (int s = 0; s < 5; ++s) {
         pr[s] = value(q, i - 2 + s, j);
@@ -658,7 +686,7 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
       }
       res -= convection_term(g.scheme, Cr, pr);
       res -= convection_term(g.scheme, Ct, pt);
-      out[(size_t)n * NQ + q] = res;
+      out[(size_t)n * VG.nq + q] = res;
     }
   }
 }
@@ -668,27 +696,29 @@ void or_step_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int
 void or_init_feq(const OrGrid* gp, const double* rho, const double* ur, const double* ut,
                  const double* T, double* f) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
   for (int i = 0; i < g.nr; ++i)
     for (int j = 0; j < g.nth; ++j) {
       size_t c = (size_t)i * g.nth + j;
       double ux = ur[c] * geo.ct[j] - ut[c] * geo.st[j];
       double uy = ur[c] * geo.st[j] + ut[c] * geo.ct[j];
-      double fe[NQ];
-      feq_all(rho[c], ux, uy, T[c], fe);
-      for (int q = 0; q < NQ; ++q) f[idx(g, q, i, j)] = fe[q];
+      double fe[NQ_MAX];
+      feq_all(VG, rho[c], ux, uy, T[c], fe);
+      for (int q = 0; q < VG.nq; ++q) f[idx(g, q, i, j)] = fe[q];
     }
 }
 
 // rho, u_r, u_theta, T fields of a distribution (any output may be null).
 void or_fields(const OrGrid* gp, const double* f, double* rho, double* ur, double* ut, double* T) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
   for (int i = 0; i < g.nr; ++i)
     for (int j = 0; j < g.nth; ++j) {
-      double fl[NQ], r_, ux, uy, E;
-      for (int q = 0; q < NQ; ++q) fl[q] = f[idx(g, q, i, j)];
-      macros(fl, r_, ux, uy, E);
+      double fl[NQ_MAX], r_, ux, uy, E;
+      for (int q = 0; q < VG.nq; ++q) fl[q] = f[idx(g, q, i, j)];
+      macros(VG, fl, r_, ux, uy, E);
       size_t c = (size_t)i * g.nth + j;
       if (rho) rho[c] = r_;
       if (ur) ur[c] = ux * geo.ct[j] + uy * geo.st[j];
@@ -703,6 +733,7 @@ void or_fields(const OrGrid* gp, const double* f, double* rho, double* ur, doubl
 // Sums are accumulated in long double.
 void or_diagnostics(const OrGrid* gp, const double* f, double* out) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
   long double mass = 0, px = 0, py = 0, en = 0;
   double rmin = INFINITY, tmin = INFINITY, bad = 0;
@@ -710,19 +741,19 @@ void or_diagnostics(const OrGrid* gp, const double* f, double* out) {
     double w = (i == 0 || i == g.nr - 1) ? 0.5 : 1.0;
     double dA = geo.rr(i) * w * geo.dr * geo.dth;
     for (int j = 0; j < g.nth; ++j) {
-      double fl[NQ];
+      double fl[NQ_MAX];
       long double rho = 0, jx = 0, jy = 0, eps = 0;
       bool fin = true;
-      for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < VG.nq; ++q) {
         fl[q] = f[idx(g, q, i, j)];
         if (!std::isfinite(fl[q])) fin = false;
-        rho += fl[q]; jx += fl[q] * V.vx[q]; jy += fl[q] * V.vy[q];
-        eps += 0.5L * fl[q] * (V.vx[q] * V.vx[q] + V.vy[q] * V.vy[q]);
+        rho += fl[q]; jx += fl[q] * VG.vx[q]; jy += fl[q] * VG.vy[q];
+        eps += 0.5L * fl[q] * (VG.vx[q] * VG.vx[q] + VG.vy[q] * VG.vy[q]);
       }
       if (!fin) { bad += 1; continue; }
       mass += rho * dA; px += jx * dA; py += jy * dA; en += eps * dA;
       double r_, ux, uy, E;
-      macros(fl, r_, ux, uy, E);
+      macros(VG, fl, r_, ux, uy, E);
       rmin = std::min(rmin, r_); tmin = std::min(tmin, E);
     }
   }
@@ -740,13 +771,15 @@ void or_diagnostics(const OrGrid* gp, const double* f, double* out) {
 int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next, double tie_eps,
                     double* lam_out) {
   const OrGrid& g = *gp;
-  // the adjoint of the combined MWB step with equilibrium ghosts only
-  if (g.scheme != 0 || g.terms != 7 || (g.bc_kind[0] & 16) || (g.bc_kind[1] & 16)) return -1;
+  const Velocities& VG = vel_of(g.ni);
+  // the adjoint of the combined MWB step of the octagon with equilibrium ghosts only
+  if (g.scheme != 0 || g.terms != 7 || (g.bc_kind[0] & 16) || (g.bc_kind[1] & 16) || g.ni != 8)
+    return -1;
   Geometry geo(g);
-  size_t tot = (size_t)NQ * g.nr * g.nth, n = (size_t)g.nr * g.nth;
+  size_t tot = (size_t)VG.nq * g.nr * g.nth, n = (size_t)g.nr * g.nth;
   std::vector<double> m;
   all_macros(g, f_t, m);
-  Padded P(g.nr, g.nth);
+  Padded P(g.nr, g.nth, VG.nq);
   build_padded(g, geo, f_t, m, P);
   // d(relaxed f)/df = e + (1 - e) df^eq/df for both relaxations: Eq.
   // operator1_new has e = exp(-dt/tau), Eq. operator1_old e = 1 - dt/tau
@@ -756,7 +789,7 @@ int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next,
   std::vector<double> gM((size_t)4 * n, 0.0);
   // adjoint of the radial ghost distributions: [q][row slot 0..3][j] with
   // slots (-2, -1, nr, nr+1)
-  std::vector<double> gG((size_t)NQ * 4 * g.nth, 0.0);
+  std::vector<double> gG((size_t)VG.nq * 4 * g.nth, 0.0);
   std::fill(lam_out, lam_out + tot, 0.0);
 
   // (1) relaxation: lam_out += e lam; f^eq path into the node's moments.
@@ -764,21 +797,21 @@ int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next,
   for (int i = 0; i < g.nr; ++i)
     for (int j = 0; j < g.nth; ++j) {
       size_t c = (size_t)i * g.nth + j;
-      double fl[NQ];
-      for (int q = 0; q < NQ; ++q) fl[q] = f_t[idx(g, q, i, j)];
+      double fl[NQ_MAX];
+      for (int q = 0; q < VG.nq; ++q) fl[q] = f_t[idx(g, q, i, j)];
       Dual<4> M[4];
       M[0] = 0; M[1] = 0; M[2] = 0; M[3] = 0;
       double Mv[4] = {0, 0, 0, 0};
-      for (int q = 0; q < NQ; ++q) {
-        Mv[0] += fl[q]; Mv[1] += fl[q] * V.vx[q]; Mv[2] += fl[q] * V.vy[q];
-        Mv[3] += 0.5 * fl[q] * (V.vx[q] * V.vx[q] + V.vy[q] * V.vy[q]);
+      for (int q = 0; q < VG.nq; ++q) {
+        Mv[0] += fl[q]; Mv[1] += fl[q] * VG.vx[q]; Mv[2] += fl[q] * VG.vy[q];
+        Mv[3] += 0.5 * fl[q] * (VG.vx[q] * VG.vx[q] + VG.vy[q] * VG.vy[q]);
       }
       for (int a = 0; a < 4; ++a) { M[a] = Dual<4>(Mv[a]); M[a].d[a] = 1.0; }
-      Dual<4> rho, ux, uy, E, fe[NQ];
+      Dual<4> rho, ux, uy, E, fe[NQ_MAX];
       macros_of_M(M, rho, ux, uy, E);
-      feq_all(rho, ux, uy, E, fe);
+      feq_all(VG, rho, ux, uy, E, fe);
       double acc[4] = {0, 0, 0, 0};
-      for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < VG.nq; ++q) {
         double lam = lam_next[idx(g, q, i, j)];
         lam_out[idx(g, q, i, j)] += e * lam;
         for (int a = 0; a < 4; ++a) acc[a] += (1.0 - e) * lam * fe[q].d[a];
@@ -796,8 +829,8 @@ int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next,
       double r = geo.rr(i);
       for (int j = 0; j < g.nth; ++j) {
         double lam = lam_next[idx(g, q, i, j)];
-        double Cr = vr_of(q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
-        double Ct = vt_of(q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
+        double Cr = vr_of(VG, q, geo.ct[j], geo.st[j]) * g.dt / geo.dr;
+        double Ct = vt_of(VG, q, geo.ct[j], geo.st[j]) * g.dt / (r * geo.dth);
         double psi[5], gr[5];
         for (int s = 0; s < 5; ++s) psi[s] = P.at(q, i - 2 + s, j);
         mwb_grad(Cr, psi, tie_eps, gr);
@@ -831,9 +864,9 @@ int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next,
       Dual<8> M0[4], M1[4], m0[4], m1[4], o1[4], o2[4];
       for (int a = 0; a < 4; ++a) {
         double v0 = 0, v1 = 0;
-        for (int q = 0; q < NQ; ++q) {
-          double ph = a == 0 ? 1.0 : a == 1 ? V.vx[q] : a == 2 ? V.vy[q]
-                    : 0.5 * (V.vx[q] * V.vx[q] + V.vy[q] * V.vy[q]);
+        for (int q = 0; q < VG.nq; ++q) {
+          double ph = a == 0 ? 1.0 : a == 1 ? VG.vx[q] : a == 2 ? VG.vy[q]
+                    : 0.5 * (VG.vx[q] * VG.vx[q] + VG.vy[q] * VG.vy[q]);
           v0 += ph * f_t[idx(g, q, i0, j)];
           v1 += ph * f_t[idx(g, q, i1, j)];
         }
@@ -843,11 +876,11 @@ int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next,
       macros_of_M(M0, m0[0], m0[1], m0[2], m0[3]);
       macros_of_M(M1, m1[0], m1[1], m1[2], m1[3]);
       ghost_macros<Dual<8>>(g, side, geo.rr(ig1), geo.rr(ig2), geo.ct[j], geo.st[j], m0, m1, o1, o2);
-      Dual<8> fe1[NQ], fe2[NQ];
-      feq_all(o1[0], o1[1], o1[2], o1[3], fe1);
-      feq_all(o2[0], o2[1], o2[2], o2[3], fe2);
+      Dual<8> fe1[NQ_MAX], fe2[NQ_MAX];
+      feq_all(VG, o1[0], o1[1], o1[2], o1[3], fe1);
+      feq_all(VG, o2[0], o2[1], o2[2], o2[3], fe2);
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < VG.nq; ++q) {
         double l1 = gG[((size_t)q * 4 + s1) * g.nth + j];
         double l2 = gG[((size_t)q * 4 + s2) * g.nth + j];
         for (int d = 0; d < 8; ++d) acc[d] += l1 * fe1[q].d[d] + l2 * fe2[q].d[d];
@@ -864,9 +897,9 @@ int or_adjoint_step(const OrGrid* gp, const double* f_t, const double* lam_next,
   for (int i = 0; i < g.nr; ++i)
     for (int j = 0; j < g.nth; ++j) {
       size_t c = (size_t)i * g.nth + j;
-      for (int q = 0; q < NQ; ++q) {
-        double ph3 = 0.5 * (V.vx[q] * V.vx[q] + V.vy[q] * V.vy[q]);
-        lam_out[idx(g, q, i, j)] += gM[c] + gM[n + c] * V.vx[q] + gM[2 * n + c] * V.vy[q] +
+      for (int q = 0; q < VG.nq; ++q) {
+        double ph3 = 0.5 * (VG.vx[q] * VG.vx[q] + VG.vy[q] * VG.vy[q]);
+        lam_out[idx(g, q, i, j)] += gM[c] + gM[n + c] * VG.vx[q] + gM[2 * n + c] * VG.vy[q] +
                                     gM[3 * n + c] * ph3;
       }
     }
@@ -879,6 +912,7 @@ void or_adjoint_init(const OrGrid* gp, const double* rho, const double* ur, cons
                      const double* T, const double* lam, double* d_rho, double* d_ur,
                      double* d_ut, double* d_T) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
   for (int i = 0; i < g.nr; ++i)
     for (int j = 0; j < g.nth; ++j) {
@@ -887,10 +921,10 @@ void or_adjoint_init(const OrGrid* gp, const double* rho, const double* ur, cons
       R.d[0] = 1; Ur.d[1] = 1; Ut.d[2] = 1; TT.d[3] = 1;
       Dual<4> ux = Ur * geo.ct[j] - Ut * geo.st[j];
       Dual<4> uy = Ur * geo.st[j] + Ut * geo.ct[j];
-      Dual<4> fe[NQ];
-      feq_all(R, ux, uy, TT, fe);
+      Dual<4> fe[NQ_MAX];
+      feq_all(VG, R, ux, uy, TT, fe);
       double acc[4] = {0, 0, 0, 0};
-      for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < VG.nq; ++q) {
         double l = lam[idx(g, q, i, j)];
         for (int a = 0; a < 4; ++a) acc[a] += l * fe[q].d[a];
       }
@@ -911,17 +945,18 @@ void or_adjoint_init(const OrGrid* gp, const double* rho, const double* ur, cons
 // The non-equilibrium fields of one node (i, j): acc[kind][12] as or_noneq.
 static void noneq_node(const OrGrid& g, const Geometry& geo, const double* f, int i, int j,
                        double acc[4][12]) {
-  double fl[NQ], fe[NQ];
-  for (int q = 0; q < NQ; ++q) fl[q] = f[idx(g, q, i, j)];
+  const Velocities& VG = vel_of(g.ni);
+  double fl[NQ_MAX], fe[NQ_MAX];
+  for (int q = 0; q < VG.nq; ++q) fl[q] = f[idx(g, q, i, j)];
   double rho, ux, uy, E;
-  macros(fl, rho, ux, uy, E);
-  feq_all(rho, ux, uy, E, fe);
+  macros(VG, fl, rho, ux, uy, E);
+  feq_all(VG, rho, ux, uy, E, fe);
   const double ct = geo.ct[j], st = geo.st[j];
   const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
   for (int a = 0; a < 4; ++a)
     for (int c = 0; c < 12; ++c) acc[a][c] = 0.0;
-  for (int q = 0; q < NQ; ++q) {
-    const double vr = vr_of(q, ct, st), vt = vt_of(q, ct, st);
+  for (int q = 0; q < VG.nq; ++q) {
+    const double vr = vr_of(VG, q, ct, st), vt = vt_of(VG, q, ct, st);
     for (int kind = 0; kind < 4; ++kind) {
       const double w = kind < 2 ? fl[q] : fl[q] - fe[q];       // f, or f - f^eq
       const bool central = kind % 2 == 1;
@@ -949,6 +984,7 @@ static void noneq_node(const OrGrid& g, const Geometry& geo, const double* f, in
 // 3 = Delta*.
 void or_noneq(const OrGrid* gp, const double* f, double* out) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
   const size_t n = (size_t)g.nr * g.nth;
 #pragma omp parallel for schedule(static)
@@ -967,6 +1003,7 @@ void or_noneq(const OrGrid* gp, const double* f, double* out) {
 void or_noneq_sample(const OrGrid* gp, const double* f, const int32_t* nodes, int32_t count,
                      double* out) {
   const OrGrid& g = *gp;
+  const Velocities& VG = vel_of(g.ni);
   Geometry geo(g);
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < count; ++n) {

@@ -18,6 +18,7 @@ struct OrGrid {
   int32_t terms;
   int32_t nf;
   int32_t scheme, relax;
+  int32_t ni;
 };
 
 extern "C" {
@@ -74,7 +75,7 @@ int main() {
   for (const auto& kd : kinds)
   for (int nf : {8, 1, 3}) {
     OrGrid g{nr, nth, 0.5, 1.5, 2e-3, 1e-3, {kd[0], kd[1]}, {{0.2, 0, 0, 0}, {1.05, 0.02, 0.01, 0.95}}, 7, nf,
-             0, nf == 3 ? 1 : 0};
+             0, nf == 3 ? 1 : 0, 8};
     if (kd[0] == 1) { g.bc_par[0][0] = 1.1; g.bc_par[0][1] = 0.05; g.bc_par[0][2] = 0.0; g.bc_par[0][3] = 1.0; }
     std::vector<double> rho(n), ur(n), ut(n), T(n);
     for (int i = 0; i < nr; ++i)
