@@ -131,6 +131,36 @@ def run_variants(W, Sim, torch, steps=20, warmup=3):
     return out
 
 
+def run_models(W, Sim, torch, steps=20, warmup=3):
+    """Step time of the double and triple octagon (Table I rows 2 and 3: 65
+    and 97 velocities) on the headline workload's grid, both precisions.
+    Algorithmic bytes per step: each velocity value read once and written
+    once."""
+    import dataclasses
+    P0, F = W.kelvin_helmholtz(4096, 8192, steps)
+    nodes = P0.nr * P0.nth
+    out = {}
+    for ni in (16, 24):
+        P = dataclasses.replace(P0, ni=ni, nf=ni)
+        nq = 1 + 4 * ni
+        for prec in (32, 64):
+            sim = Sim(P, precision=prec)
+            sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+            sim.step(warmup)
+            ms = time_steps(sim, torch, steps)
+            d = sim.diagnostics_host()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+            byts = 2 * nq * nodes * (prec // 8)
+            out[f"ni{ni}_fp{prec}"] = {
+                "velocities": nq, "ms_per_step": ms,
+                "gcellvel_per_s": nq * nodes / (ms * 1e-3) / 1e9,
+                "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "finite": bool(d[6] == 0)}
+    return out
+
+
 def couette_errors(W, Sim, torch):
     """Sec. III.A: the one-eighth-sector rotating-cylinder run (100 x 20) from
     rest to steady state in FP64 for each relaxation time; the largest
@@ -487,6 +517,9 @@ def main():
     ap.add_argument("--variants-only", action="store_true",
                     help="step time per convection scheme, the non-equilibrium fields kernel, "
                          "the Couette errors and the sector Richtmyer-Meshkov runs, then exit")
+    ap.add_argument("--models-only", action="store_true",
+                    help="time the double and triple octagon (65 and 97 velocities) on the "
+                         "headline grid and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -524,6 +557,9 @@ def main():
     if args.accuracy_only:
         for name in ACCURACY_RUNS:
             print(json.dumps({name: fp32_accuracy(W, torch, name)}), flush=True)
+        return
+    if args.models_only:
+        print(json.dumps({"double_triple_octagon_kh4096x8192": run_models(W, Sim, torch)}), flush=True)
         return
     if args.variants_only:
         print(json.dumps({"schemes_and_noneq_kh4096x8192_fp32": run_variants(W, Sim, torch)}),
@@ -569,6 +605,7 @@ def main():
         extra["fp32_error_vs_fp64_after_run"] = {name: fp32_accuracy(W, torch, name)
                                                  for name in ACCURACY_RUNS}
         extra["schemes_and_noneq_kh4096x8192_fp32"] = run_variants(W, Sim, torch)
+        extra["double_triple_octagon_kh4096x8192"] = run_models(W, Sim, torch)
         extra["couette_sector_steady_error"] = couette_errors(W, Sim, torch)
         extra["rm_sector_compression"] = rm_sector_runs(W, Sim)
     out["extra"] = extra

@@ -4,23 +4,28 @@
  * The library advances the 33 discrete-velocity distributions f_q of the
  * octagon velocity model (Lin, Xu, Zhang, Li, Succi, "Polar coordinate lattice
  * Boltzmann modeling of compressible flows", arXiv:1302.7104, Sec. II.A,
- * Eq. DVM1 and Table I row 1) on an annulus R1 <= r <= R2 (Sec. II.C) with the
- * combined scheme of Sec. II.B (Eq. combined_scheme): analytic BGK relaxation
- * (Eq. operator1_new) plus the Modified Warming-Beam convection terms in r and
+ * Eq. DVM1 and Table I row 1), or the 65 and 97 of the double and triple
+ * octagon (Table I rows 2 and 3, pclb_config.n_i = 16 and 24), on an annulus
+ * R1 <= r <= R2 or a sector of it (Sec. II.C) with the combined scheme of
+ * Sec. II.B (Eq. combined_scheme): analytic BGK relaxation (Eq.
+ * operator1_new) plus the Modified Warming-Beam convection terms in r and
  * theta (Eq. MWB Scheme with the switch S(eta) = (|eta|-1)/(|eta|+1)), all
- * evaluated from f at time t.  Boundaries: periodic in theta over the full
- * circle (Sec. II.C, azimuthal boundary condition with N_f = N_i), and two
- * radial ghost layers per wall holding equilibria of linearly extrapolated
- * density and temperature (Sec. II.C, radial boundary condition).
+ * evaluated from f at time t.  Boundaries: periodic in theta (Sec. II.C,
+ * azimuthal boundary condition, with the direction rotation of a sector), and
+ * two radial ghost layers per wall holding equilibria of linearly
+ * extrapolated density and temperature (Sec. II.C, radial boundary
+ * condition).
  *
  * Conventions shared by every entry point
  * ----------------------------------------
- *  - Distribution arrays are structure-of-arrays f[q][i][j] with q = 0..32
- *    (q = 0 rest; q = 1 + 8(k-1) + d for speed group k = 1..4 and direction
- *    d = 0..7 at angle d*pi/4), i = 0..n_r-1 radial (r_i = R1 + i*dr,
+ *  - Distribution arrays are structure-of-arrays f[q][i][j] with
+ *    q = 0..4 n_i (q = 0 rest; q = 1 + n_i(k-1) + d for speed group k = 1..4
+ *    and direction d = 0..n_i-1 at angle 2 pi d / n_i; the octagon: q = 0..32,
+ *    angle d*pi/4), i = 0..n_r-1 radial (r_i = R1 + i*dr,
  *    dr = (R2-R1)/(n_r-1)), j = 0..n_theta-1 azimuthal (theta_j =
- *    (j+1)*2pi/n_theta), j fastest.  Element type: float when the context was
- *    created with precision 32, double with precision 64.
+ *    (j+1)*dtheta, dtheta = 2 pi n_f / (n_i n_theta)), j fastest.  Element
+ *    type: float when the context was created with precision 32, double
+ *    with precision 64.
  *  - Field arrays (rho, u_r, u_theta, T and their cotangents) are double
  *    [n_r][n_theta].  Velocities are polar components at each node.
  *    T is the temperature, equal to the internal energy E since gamma = 2
@@ -72,7 +77,9 @@ enum {
  * octant boundary theta = m pi/4 (none when n_theta is a multiple of 512) run
  * in a second launch of a variant that selects upwind sides per lane.
  * Everything else (double states, sectors, the comparison schemes, narrow
- * grids) runs on the node kernel, whatever is asked. */
+ * grids) runs on the node kernel, whatever is asked.  The double and triple
+ * octagon run on a kernel of their own (one thread per node, velocities in a
+ * loop) whatever is asked. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
@@ -108,11 +115,14 @@ typedef struct pclb_config {
   double r1, r2;         /* annulus radii, 0 < r1 < r2 */
   double tau;            /* relaxation time (Eq. FDLBM), > 0 */
   double dt;             /* time step, > 0 */
-  int32_t n_i;           /* directions per speed group; must be 8 (octagon) */
-  int32_t n_f;           /* N_f of Sec. II.C, 1..8: theta covers 0 < theta <= 2 pi n_f / 8,
-                            dtheta = 2 pi n_f / (8 n_theta), and for n_f < 8 the
+  int32_t n_i;           /* directions per speed group (Eq. DVM1, Table I): 8
+                            (octagon, 33 velocities), 16 (double octagon, 65) or
+                            24 (triple octagon, 97).  Non-equilibrium moments and
+                            the adjoint cover n_i = 8 only */
+  int32_t n_f;           /* N_f of Sec. II.C, 1..n_i: theta covers 0 < theta <= 2 pi n_f / n_i,
+                            dtheta = 2 pi n_f / (n_i n_theta), and for n_f < n_i the
                             azimuthal ghosts rotate the direction index by n_f
-                            (Fig. 3); 8 is the full annulus */
+                            (Fig. 3); n_f = n_i is the full annulus */
   int32_t precision;     /* 32: float storage and convection; 64: double throughout */
   int32_t fp64_collision;/* 1: moments, equilibrium and relaxation in double for
                             either precision.  The only accepted value: float
@@ -140,7 +150,8 @@ typedef struct pclb_config {
 double pclb_cfl_dt(const pclb_config* cfg, double cfl);
 
 /* Validate cfg and create a context on the current HIP device.  Checks
- * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i = 8, n_f in 1..8,
+ * r1 > 0, r2 > r1, n_r >= 4, n_theta >= 8, tau > 0, dt > 0, n_i in {8, 16, 24},
+ * n_f in 1..n_i,
  * precision in {32, 64}, fp64_collision = 1, the launch-shape fields,
  * adjoint_tie, scheme and relaxation in range (PCLB_EINVAL), and
  * max |C_r|, |C_theta| <= 1 (the
@@ -157,9 +168,10 @@ void pclb_destroy(pclb_ctx* ctx);
  * is NULL).  Static lifetime until the next call on the same context. */
 const char* pclb_last_error(const pclb_ctx* ctx);
 
-/* Bind two caller-owned device buffers of 33*n_r*n_theta elements each (the
- * ping-pong pair) and the HIP stream (a hipStream_t, NULL = default stream)
- * on which every later call enqueues its work.  Buffer 0 becomes current. */
+/* Bind two caller-owned device buffers of (1 + 4 n_i)*n_r*n_theta elements
+ * each (33, 65 or 97 planes; the ping-pong pair) and the HIP stream (a
+ * hipStream_t, NULL = default stream) on which every later call enqueues its
+ * work.  Buffer 0 becomes current. */
 int pclb_bind(pclb_ctx* ctx, void* f0, void* f1, void* stream);
 
 /* Set the radial boundary of side 0 (inner, r = R1) or 1 (outer, r = R2):
@@ -187,9 +199,10 @@ int pclb_step(pclb_ctx* ctx, int64_t n);
  * same steps, bit for bit, with the radial ghost layers held in a static
  * scratch array of the library (16 MiB per GPU, reserved while the library is
  * loaded) instead of the context's buffer.  Calls no allocating routine.
- * Returns PCLB_EINVAL if the ghost layers (4 * 33 * n_theta elements of the
- * state type) exceed the array, i.e. n_theta > 31775 at precision 32 or
- * n_theta > 15887 at precision 64.  Every call on one GPU, from any context,
+ * Returns PCLB_EINVAL if the ghost layers (4 * (1 + 4 n_i) * n_theta elements
+ * of the state type) exceed the array: for the octagon n_theta > 31775 at
+ * precision 32 or n_theta > 15887 at precision 64 (65 and 97 velocities:
+ * 16131 and 10810 at precision 32, half that at 64).  Every call on one GPU, from any context,
  * uses that GPU's one array: calls that overlap in time on one GPU (other
  * streams, other threads) race and must not be issued. */
 int pclb_step_static(pclb_ctx* ctx, int64_t n);

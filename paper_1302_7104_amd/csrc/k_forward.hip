@@ -2,6 +2,7 @@
 // reference step, initial equilibrium, macroscopic fields and diagnostics.
 // Sec. II of Lin et al. (arXiv:1302.7104).
 #include "common.h"
+#include "diag.h"
 #include "launch.h"
 
 namespace pclb {
@@ -217,28 +218,7 @@ __global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Diagnostics: compensated per-thread sums, a block tree of (sum, error)
-// pairs, and a one-block fixed-order final pass (deterministic).
-struct TwoS {
-  double s, c;
-};
-__device__ inline void two_add(TwoS& a, double x) {
-  double s = a.s + x;
-  double bb = s - a.s;
-  double err = (a.s - (s - bb)) + (x - bb);
-  a.s = s;
-  a.c += err;
-}
-__device__ inline TwoS two_merge(TwoS a, TwoS b) {
-  TwoS r = a;
-  two_add(r, b.s);
-  r.c += b.c;
-  return r;
-}
-
-constexpr int DIAG_BLOCK = 256;
-constexpr int DIAG_SLOTS = 11;   // 4 x (sum, err), min rho, min T, bad count
-
+// Diagnostics of the octagon state (reduction helpers in diag.h).
 template <class R>
 __global__ void __launch_bounds__(DIAG_BLOCK) diag_partial_kernel(Tables T, const R* __restrict__ f,
                                                                   double* __restrict__ partial) {
@@ -273,29 +253,7 @@ __global__ void __launch_bounds__(DIAG_BLOCK) diag_partial_kernel(Tables T, cons
     rmin = fmin(rmin, rho);
     tmin = fmin(tmin, E);
   }
-  __shared__ double sh[DIAG_SLOTS][DIAG_BLOCK];
-  for (int a = 0; a < 4; ++a) { sh[2 * a][threadIdx.x] = acc[a].s; sh[2 * a + 1][threadIdx.x] = acc[a].c; }
-  sh[8][threadIdx.x] = rmin;
-  sh[9][threadIdx.x] = tmin;
-  sh[10][threadIdx.x] = bad;
-  __syncthreads();
-  for (int w = DIAG_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      int o = threadIdx.x + w;
-      for (int a = 0; a < 4; ++a) {
-        TwoS x{sh[2 * a][threadIdx.x], sh[2 * a + 1][threadIdx.x]};
-        TwoS y{sh[2 * a][o], sh[2 * a + 1][o]};
-        TwoS z = two_merge(x, y);
-        sh[2 * a][threadIdx.x] = z.s;
-        sh[2 * a + 1][threadIdx.x] = z.c;
-      }
-      sh[8][threadIdx.x] = fmin(sh[8][threadIdx.x], sh[8][o]);
-      sh[9][threadIdx.x] = fmin(sh[9][threadIdx.x], sh[9][o]);
-      sh[10][threadIdx.x] += sh[10][o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < DIAG_SLOTS) partial[(size_t)blockIdx.x * DIAG_SLOTS + threadIdx.x] = sh[threadIdx.x][0];
+  diag_block_reduce(acc, rmin, tmin, bad, partial);
 }
 
 __global__ void __launch_bounds__(64) diag_final_kernel(const double* __restrict__ partial, int nb,
@@ -380,6 +338,10 @@ hipError_t launch_diag(const Tables& T, const void* f, double* partial, double s
   hipLaunchKernelGGL(diag_partial_kernel<R>, dim3(nb), dim3(DIAG_BLOCK), 0, s, T, (const R*)f, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_diag_final(partial, nb, step, out, s);
+}
+
+hipError_t launch_diag_final(const double* partial, int nb, double step, double* out, hipStream_t s) {
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partial, nb, step, out);
   return hipGetLastError();
 }

@@ -1,0 +1,465 @@
+// The double and triple octagon models (Sec. II.A: Eq. DVM1 with N_i = 16 or
+// 24 directions per speed, the weights of Table I's second and third rows):
+// radial ghost layers, step, initial state, fields and diagnostics for 65 and
+// 97 velocities.  One thread per node, the velocities visited in runtime loops
+// (the velocity count makes fully unrolled code, as the octagon kernels use,
+// impractical), every neighbour read from global memory.  The arithmetic per
+// velocity is the octagon's: moments and equilibrium in double, f^eq =
+// rho F_k P(w), the relaxation e f + (1 - e) f^eq, the scheme's two convection
+// terms (conv_term) in the state type, one rounding.  Upwind sides follow the
+// signs of the computed velocity components (a component that vanishes exactly
+// has |C| of the order of the rounding there, so its side moves no result
+// beyond that size).  State layout f[q][i][j] with q = 1 + N_i (k - 1) + d;
+// ghost layers ghost[side][layer][q][j] with 1 + 4 N_i planes.
+#include "common.h"
+#include "diag.h"
+#include "launch.h"
+
+namespace pclb {
+
+namespace {
+
+// cos and sin of 2 pi d / N for d = 0..N-1 (N a multiple of 8), formed at
+// compile time: the angle is split into o eighths of the circle and a
+// remainder x in [0, pi/4), whose series are summed to full double precision
+// (the 14th term is below 1e-40), then rotated by the o eighths.
+constexpr double CPI = 3.14159265358979323846;
+constexpr double series_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double series_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+constexpr void dir_cs(int d, int N, double& c, double& s) {
+  const int n = N / 8, o = d / n, m = d % n;
+  const double x = CPI / 4.0 * m / n;
+  const double a = m == 0 ? 1.0 : series_cos(x), b = m == 0 ? 0.0 : series_sin(x);
+  const double h = RSQRT2;
+  switch (o) {
+    case 0: c = a; s = b; break;
+    case 1: c = (a - b) * h; s = (a + b) * h; break;
+    case 2: c = -b; s = a; break;
+    case 3: c = -(a + b) * h; s = (a - b) * h; break;
+    case 4: c = -a; s = -b; break;
+    case 5: c = (b - a) * h; s = -(a + b) * h; break;
+    case 6: c = b; s = -a; break;
+    default: c = (a + b) * h; s = (b - a) * h;
+  }
+}
+template <int NI> struct Dirs {
+  double c[NI], s[NI];
+  constexpr Dirs() : c(), s() {
+    for (int d = 0; d < NI; ++d) dir_cs(d, NI, c[d], s[d]);
+  }
+};
+// compile-time checks of the tables against values known to 20 digits, and
+// of |e_d| = 1 for every direction
+constexpr double cabs(double x) { return x < 0 ? -x : x; }
+template <int NI> constexpr bool unit_dirs() {
+  const Dirs<NI> t{};
+  for (int d = 0; d < NI; ++d)
+    if (cabs(t.c[d] * t.c[d] + t.s[d] * t.s[d] - 1.0) > 4.5e-16) return false;
+  return true;
+}
+static_assert(cabs(Dirs<16>().c[1] - 0.92387953251128675613) < 2.3e-16, "cos(pi/8)");
+static_assert(cabs(Dirs<16>().s[1] - 0.38268343236508977173) < 1.2e-16, "sin(pi/8)");
+static_assert(cabs(Dirs<16>().c[13] - 0.38268343236508977173) < 1.2e-16, "cos(13 pi/8)");
+static_assert(cabs(Dirs<16>().s[13] + 0.92387953251128675613) < 2.3e-16, "sin(13 pi/8)");
+static_assert(cabs(Dirs<24>().c[1] - 0.96592582628906828675) < 2.3e-16, "cos(pi/12)");
+static_assert(cabs(Dirs<24>().s[2] - 0.5) < 1.2e-16, "sin(pi/6)");
+static_assert(cabs(Dirs<24>().c[10] + 0.86602540378443864676) < 2.3e-16, "cos(5 pi/6)");
+static_assert(cabs(Dirs<24>().s[17] + 0.96592582628906828675) < 2.3e-16, "sin(17 pi/12)");
+static_assert(unit_dirs<16>() && unit_dirs<24>(), "unit directions");
+
+__constant__ Dirs<16> DIRS16 = Dirs<16>();
+__constant__ Dirs<24> DIRS24 = Dirs<24>();
+template <int NI> __device__ inline const Dirs<NI>& dirs();
+template <> __device__ inline const Dirs<16>& dirs<16>() { return DIRS16; }
+template <> __device__ inline const Dirs<24>& dirs<24>() { return DIRS24; }
+
+// Weights F_k(E) of Table I's row for N_i (Eqs. F_k), as polynomials
+// E (c0 + E (c1 + E (c2 + E c3))) with coefficients formed at compile time
+// (the octagon's construction with that row's B1..B4); F_0 = 1 - B0 sum F_k.
+struct RowB {
+  double b0, b1, b2, b3, b4;
+};
+template <int NI> constexpr RowB row_b();
+template <> constexpr RowB row_b<16>() { return {16.0, -1.0 / 8.0, 0.5, -3.0, 24.0}; }
+template <> constexpr RowB row_b<24>() { return {24.0, -1.0 / 12.0, 1.0 / 3.0, -2.0, 16.0}; }
+// coefficient N of F_k, k = K + 1
+template <int NI> constexpr double row_coef(int K, int N) {
+  const RowB B = row_b<NI>();
+  double x[NK + 1] = {};
+  for (int k = 0; k <= NK; ++k) x[k] = speed(k) * speed(k);
+  const int k = K + 1;
+  int o[3] = {};
+  for (int l = 1; l <= 3; ++l) o[l - 1] = (k + l <= NK) ? k + l : k + l - NK;
+  const double a = x[o[0]], b = x[o[1]], c = x[o[2]];
+  const double den = x[k] * (x[k] - a) * (x[k] - b) * (x[k] - c);
+  return N == 0 ? B.b1 * a * b * c / den
+       : N == 1 ? B.b2 * (a * b + b * c + c * a) / den
+       : N == 2 ? B.b3 * (a + b + c) / den
+       : B.b4 / den;
+}
+template <int NI, int K, int N> struct RC {
+  static constexpr double v = row_coef<NI>(K, N);
+};
+template <int NI, int K>
+__device__ inline double row_weight(double E) {
+  return E * (RC<NI, K, 0>::v + E * (RC<NI, K, 1>::v + E * (RC<NI, K, 2>::v + E * RC<NI, K, 3>::v)));
+}
+
+template <int NI> constexpr int nq_of() { return 1 + NK * NI; }
+
+// Equilibrium coefficients of one node (Eq. feq in the factorised form of the
+// octagon kernels): rho F_k and P(w) = A0 + A1 w + ... + A4 w^4, w = v . u.
+struct Eq {
+  double rF[NK + 1];
+  double A0, A1, A2, A3, A4, ux, uy;
+};
+template <int NI>
+__device__ inline void eq_of(double rho, double ux, double uy, double E, Eq& c) {
+  const double F1 = row_weight<NI, 0>(E), F2 = row_weight<NI, 1>(E);
+  const double F3 = row_weight<NI, 2>(E), F4 = row_weight<NI, 3>(E);
+  c.rF[1] = rho * F1;
+  c.rF[2] = rho * F2;
+  c.rF[3] = rho * F3;
+  c.rF[4] = rho * F4;
+  c.rF[0] = rho * (1.0 - row_b<NI>().b0 * (((F1 + F2) + F3) + F4));
+  const double iE = 1.0 / E, u2 = ux * ux + uy * uy, a = 0.5 * u2 * iE, g = 1.0 - a;
+  const double iE2 = iE * iE;
+  c.A0 = g + 0.5 * a * a;
+  c.A1 = g * iE;
+  c.A2 = 0.5 * g * iE2;
+  c.A3 = iE2 * iE * (1.0 / 6.0);
+  c.A4 = iE2 * iE2 * (1.0 / 24.0);
+  c.ux = ux;
+  c.uy = uy;
+}
+// f^eq of velocity (K, d); K = 0 is the rest velocity.
+template <int NI, int K>
+__device__ inline double feq_kd(const Eq& c, int d) {
+  if constexpr (K == 0) {
+    return c.rF[0] * c.A0;
+  } else {
+    const double w = speed(K) * (c.ux * dirs<NI>().c[d] + c.uy * dirs<NI>().s[d]);
+    return c.rF[K] * (c.A0 + w * (c.A1 + w * (c.A2 + w * (c.A3 + w * c.A4))));
+  }
+}
+
+// fn(k, d, q) for every moving velocity: the speed group k as a compile-time
+// constant (so that per-speed coefficients stay in registers), the direction
+// d in a runtime loop.
+template <int NI, class Fn>
+__device__ inline void for_each_moving(Fn&& fn) {
+  for_k<1>([&](auto kc) {
+#pragma unroll 1
+    for (int d = 0; d < NI; ++d) fn(kc, d, 1 + NI * (decltype(kc)::value - 1) + d);
+  });
+}
+
+// rho, u, E of one node (Eqs. moment1-moment3) from its values get(q).
+template <int NI, class Get>
+__device__ inline void moments_of(Get get, double& rho, double& ux, double& uy, double& E,
+                                  double* jeps = nullptr) {
+  double r = get(0), jx = 0.0, jy = 0.0, eps = 0.0;
+  for_each_moving<NI>([&](auto kc, int d, int q) {
+    constexpr int k = decltype(kc)::value;
+    const double x = get(q);
+    r += x;
+    jx += x * (speed(k) * dirs<NI>().c[d]);
+    jy += x * (speed(k) * dirs<NI>().s[d]);
+    eps += x * (speed(k) * speed(k));
+  });
+  rho = r;
+  const double ir = 1.0 / r;
+  ux = jx * ir;
+  uy = jy * ir;
+  E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
+  if (jeps) {
+    jeps[0] = jx;
+    jeps[1] = jy;
+    jeps[2] = 0.5 * eps;
+  }
+}
+
+__device__ inline size_t gidx(int side, int layer, int q, int j, int nth, int nq) {
+  return ((size_t)(side * 2 + layer) * nq + q) * (size_t)nth + j;
+}
+
+// The velocity whose plane a ghost column beyond the ends of a sector reads
+// (Sec. II.C, Fig. 3): direction d -> (d + s) mod N_i, speed unchanged.
+template <int NI>
+__device__ inline int rotq(int q, int s) {
+  if (q == 0 || s == 0) return q;
+  const int k = (q - 1) / NI, d = (q - 1) % NI;
+  return 1 + NI * k + (d + s) % NI;
+}
+
+// Radial ghost layers (Sec. II.C): rho, u, E of the two rows next to the wall
+// extrapolated linearly and recursively, u set per boundary kind, f^eq of the
+// ghost state stored; with bc.neq the wall row's f - f^eq is added.
+template <class R, int NI>
+__global__ void __launch_bounds__(256) models_ghost_kernel(Tables T, BCdev bc, const R* __restrict__ f,
+                                                           R* __restrict__ ghost) {
+  constexpr int NQM = nq_of<NI>();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int side = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  const int i0 = side == 0 ? 0 : T.nr - 1, i1 = side == 0 ? 1 : T.nr - 2;
+  const R* f0 = f + (size_t)i0 * T.nth + j;
+  const R* f1 = f + (size_t)i1 * T.nth + j;
+  double m[2][4];
+  moments_of<NI>([&](int q) { return (double)f0[q * plane]; }, m[0][0], m[0][1], m[0][2], m[0][3]);
+  moments_of<NI>([&](int q) { return (double)f1[q * plane]; }, m[1][0], m[1][1], m[1][2], m[1][3]);
+  const double ct = T.cth[j], st = T.sth[j];
+  const bool neq = bc.neq[side] != 0;
+  Eq c0{};
+  if (neq) eq_of<NI>(m[0][0], m[0][1], m[0][2], m[0][3], c0);
+  double prev[4] = {m[0][0], m[0][1], m[0][2], m[0][3]};
+  double pprev[4] = {m[1][0], m[1][1], m[1][2], m[1][3]};
+  const int kind = bc.kind[side];
+  for (int layer = 0; layer < 2; ++layer) {
+    double g[4];
+    for (int a = 0; a < 4; ++a) g[a] = 2.0 * prev[a] - pprev[a];
+    for (int a = 0; a < 4; ++a) { pprev[a] = prev[a]; prev[a] = g[a]; }
+    double rho = g[0], ux = g[1], uy = g[2], E = g[3];
+    if (kind == 0) {                   // WALL: u_r = 0, u_theta = omega r_g
+      const double ut = bc.p[side][0] * bc.rg[side][layer];
+      ux = -ut * st;
+      uy = ut * ct;
+    } else if (kind == 1) {            // INFLOW
+      rho = bc.p[side][0];
+      ux = bc.p[side][1] * ct - bc.p[side][2] * st;
+      uy = bc.p[side][1] * st + bc.p[side][2] * ct;
+      E = bc.p[side][3];
+    }                                  // EXTRAPOLATE keeps the extrapolated u
+    Eq c;
+    eq_of<NI>(rho, ux, uy, E, c);
+    const double nv0 = neq ? (double)f0[0] - feq_kd<NI, 0>(c0, 0) : 0.0;
+    ghost[gidx(side, layer, 0, j, T.nth, NQM)] = (R)(feq_kd<NI, 0>(c, 0) + nv0);
+    for_each_moving<NI>([&](auto kc, int d, int q) {
+      constexpr int k = decltype(kc)::value;
+      const double nv = neq ? (double)f0[q * plane] - feq_kd<NI, k>(c0, d) : 0.0;
+      ghost[gidx(side, layer, q, j, T.nth, NQM)] = (R)(feq_kd<NI, k>(c, d) + nv);
+    });
+  }
+}
+
+// Eq. combined_scheme for every velocity of node (i, j).
+template <class R, int NI, int SCH>
+__global__ void __launch_bounds__(256) models_step_kernel(Tables T, const R* __restrict__ f,
+                                                          R* __restrict__ out,
+                                                          const R* __restrict__ ghost) {
+  constexpr int NQM = nq_of<NI>();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int nr = T.nr, nth = T.nth;
+  if (j >= nth) return;
+  const size_t plane = (size_t)nr * nth;
+  const size_t c0 = (size_t)i * nth + j;
+  double rho, ux, uy, E;
+  moments_of<NI>([&](int q) { return (double)f[q * plane + c0]; }, rho, ux, uy, E);
+  Eq ec;
+  eq_of<NI>(rho, ux, uy, E, ec);
+  const double e = T.e, ome = 1.0 - T.e;
+  const double ct = T.cth[j], st = T.sth[j];
+  const double rinv = T.rinv[i];
+  const int s_lo = T.nf % NI, s_hi = (NI - T.nf % NI) % NI;
+  // value of velocity q at (ii, jj): radial ghost rows below 0 and above
+  // nr - 1, azimuthal wrap with the sector's direction rotation
+  auto value = [&](int q, int ii, int jj) -> R {
+    if (jj < 0) return f[rotq<NI>(q, s_lo) * plane + (size_t)ii * nth + (jj + nth)];
+    if (jj >= nth) return f[rotq<NI>(q, s_hi) * plane + (size_t)ii * nth + (jj - nth)];
+    if (ii < 0) return ghost[gidx(0, -1 - ii, q, jj, nth, NQM)];
+    if (ii >= nr) return ghost[gidx(1, ii - nr, q, jj, nth, NQM)];
+    return f[q * plane + (size_t)ii * nth + jj];
+  };
+  out[c0] = (R)fma((double)f[c0], e, ome * feq_kd<NI, 0>(ec, 0));   // rest velocity: no convection
+  for_each_moving<NI>([&](auto kc, int d, int q) {
+    constexpr int k = decltype(kc)::value;
+    const double cd = dirs<NI>().c[d], sd = dirs<NI>().s[d];
+    const double fq = (double)f[q * plane + c0];
+    const double rel = fma(fq, e, ome * feq_kd<NI, k>(ec, d));
+    const double vr = speed(k) * (cd * ct + sd * st), vt = speed(k) * (sd * ct - cd * st);
+    const R aCr = (R)(fabs(vr) * T.dt_dr), aCt = (R)(fabs(vt) * T.dt_dth * rinv);
+    const R Kr = aCr - aCr * aCr, Kt = aCt - aCt * aCt;
+    const int sr = vr >= 0.0 ? -1 : 1, sc = vt >= 0.0 ? -1 : 1;   // upwind offsets
+    const R c = (R)fq;
+    // the downwind neighbours only matter to Lax-Wendroff
+    const R wr = SCH == SCH_LW ? value(q, i - sr, j) : c;
+    const R wt = SCH == SCH_LW ? value(q, i, j - sc) : c;
+    const R tr = conv_term<SCH, R>(aCr, Kr, c, value(q, i + sr, j), value(q, i + 2 * sr, j), wr);
+    const R tt = conv_term<SCH, R>(aCt, Kt, c, value(q, i, j + sc), value(q, i, j + 2 * sc), wt);
+    out[q * plane + c0] = (R)((rel - (double)tr) - (double)tt);
+  });
+}
+
+// f = f^eq(rho, u, T), u given in polar components (Eq. feq).
+template <class R, int NI>
+__global__ void __launch_bounds__(256) models_init_kernel(Tables T, const double* __restrict__ rho,
+                                                          const double* __restrict__ ur,
+                                                          const double* __restrict__ ut,
+                                                          const double* __restrict__ Tt,
+                                                          R* __restrict__ f, int* __restrict__ bad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  const size_t c0 = (size_t)i * T.nth + j;
+  const double r = rho[c0], a = ur[c0], b = ut[c0], E = Tt[c0];
+  if (!(r > 0.0) || !(E > 0.0) || !isfinite(r) || !isfinite(E) || !isfinite(a) || !isfinite(b))
+    atomicOr(bad, 1);
+  const double ct = T.cth[j], st = T.sth[j];
+  Eq c;
+  eq_of<NI>(r, a * ct - b * st, a * st + b * ct, E, c);
+  f[c0] = (R)feq_kd<NI, 0>(c, 0);
+  for_each_moving<NI>([&](auto kc, int d, int q) {
+    f[q * plane + c0] = (R)feq_kd<NI, decltype(kc)::value>(c, d);
+  });
+}
+
+// rho, u_r, u_theta, T of every node (null outputs skipped).
+template <class R, int NI>
+__global__ void __launch_bounds__(256) models_fields_kernel(Tables T, const R* __restrict__ f,
+                                                            double* rho, double* ur, double* ut,
+                                                            double* Tt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= T.nth) return;
+  const size_t plane = (size_t)T.nr * T.nth;
+  const size_t c0 = (size_t)i * T.nth + j;
+  double r, ux, uy, E;
+  moments_of<NI>([&](int q) { return (double)f[q * plane + c0]; }, r, ux, uy, E);
+  const double ct = T.cth[j], st = T.sth[j];
+  if (rho) rho[c0] = r;
+  if (ur) ur[c0] = ux * ct + uy * st;
+  if (ut) ut[c0] = -ux * st + uy * ct;
+  if (Tt) Tt[c0] = E;
+}
+
+// Diagnostics partials in the octagon's slot layout (mass, momentum x, y and
+// energy as compensated (sum, error) pairs, min rho, min T, non-finite node
+// count), one slot row per block; the fixed-order final pass is shared.
+template <class R, int NI>
+__global__ void __launch_bounds__(DIAG_BLOCK) models_diag_kernel(Tables T, const R* __restrict__ f,
+                                                                 double* __restrict__ partial) {
+  const size_t plane = (size_t)T.nr * T.nth;
+  TwoS acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  double rmin = INFINITY, tmin = INFINITY, bad = 0.0;
+  for (size_t n = (size_t)blockIdx.x * DIAG_BLOCK + threadIdx.x; n < plane;
+       n += (size_t)gridDim.x * DIAG_BLOCK) {
+    const int i = (int)(n / T.nth);
+    bool fin = true;
+#pragma unroll 1
+    for (int q = 0; q < nq_of<NI>(); ++q) fin = fin && isfinite((double)f[q * plane + n]);
+    if (!fin) { bad += 1.0; continue; }
+    double rho, ux, uy, E, je[3];
+    moments_of<NI>([&](int q) { return (double)f[q * plane + n]; }, rho, ux, uy, E, je);
+    const double w = T.wA[i];
+    two_add(acc[0], rho * w);
+    two_add(acc[1], je[0] * w);
+    two_add(acc[2], je[1] * w);
+    two_add(acc[3], je[2] * w);
+    rmin = fmin(rmin, rho);
+    tmin = fmin(tmin, E);
+  }
+  diag_block_reduce(acc, rmin, tmin, bad, partial);
+}
+
+}  // namespace
+
+template <class R>
+hipError_t launch_models_ghost(const Tables& T, int ni, const BCdev& bc, const void* f, void* ghost,
+                               hipStream_t s) {
+  const dim3 grid((T.nth + 255) / 256, 2);
+  if (ni == 16)
+    hipLaunchKernelGGL((models_ghost_kernel<R, 16>), grid, dim3(256), 0, s, T, bc, (const R*)f, (R*)ghost);
+  else
+    hipLaunchKernelGGL((models_ghost_kernel<R, 24>), grid, dim3(256), 0, s, T, bc, (const R*)f, (R*)ghost);
+  return hipGetLastError();
+}
+
+template <class R, int NI>
+void launch_models_step_ni(const Tables& T, dim3 grid, const R* f, R* out, const R* gh, hipStream_t s) {
+  switch (T.scheme) {
+    case SCH_WB: hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_WB>), grid, dim3(256), 0, s, T, f, out, gh); break;
+    case SCH_LW: hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_LW>), grid, dim3(256), 0, s, T, f, out, gh); break;
+    case SCH_UPWIND2:
+      hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_UPWIND2>), grid, dim3(256), 0, s, T, f, out, gh);
+      break;
+    default: hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_MWB>), grid, dim3(256), 0, s, T, f, out, gh);
+  }
+}
+
+template <class R>
+hipError_t launch_models_step(const Tables& T, int ni, const void* f, void* out, const void* ghost,
+                              hipStream_t s) {
+  const dim3 grid((T.nth + 255) / 256, T.nr);
+  if (ni == 16) launch_models_step_ni<R, 16>(T, grid, (const R*)f, (R*)out, (const R*)ghost, s);
+  else launch_models_step_ni<R, 24>(T, grid, (const R*)f, (R*)out, (const R*)ghost, s);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_models_init(const Tables& T, int ni, const double* rho, const double* ur,
+                              const double* ut, const double* Tt, void* f, int* bad, hipStream_t s) {
+  const dim3 grid((T.nth + 255) / 256, T.nr);
+  if (ni == 16)
+    hipLaunchKernelGGL((models_init_kernel<R, 16>), grid, dim3(256), 0, s, T, rho, ur, ut, Tt, (R*)f, bad);
+  else
+    hipLaunchKernelGGL((models_init_kernel<R, 24>), grid, dim3(256), 0, s, T, rho, ur, ut, Tt, (R*)f, bad);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_models_fields(const Tables& T, int ni, const void* f, double* rho, double* ur,
+                                double* ut, double* Tt, hipStream_t s) {
+  const dim3 grid((T.nth + 255) / 256, T.nr);
+  if (ni == 16)
+    hipLaunchKernelGGL((models_fields_kernel<R, 16>), grid, dim3(256), 0, s, T, (const R*)f, rho, ur, ut, Tt);
+  else
+    hipLaunchKernelGGL((models_fields_kernel<R, 24>), grid, dim3(256), 0, s, T, (const R*)f, rho, ur, ut, Tt);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_models_diag(const Tables& T, int ni, const void* f, double* partial, double step,
+                              double* out, hipStream_t s) {
+  const int nb = diag_blocks();
+  if (ni == 16)
+    hipLaunchKernelGGL((models_diag_kernel<R, 16>), dim3(nb), dim3(DIAG_BLOCK), 0, s, T, (const R*)f, partial);
+  else
+    hipLaunchKernelGGL((models_diag_kernel<R, 24>), dim3(nb), dim3(DIAG_BLOCK), 0, s, T, (const R*)f, partial);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_diag_final(partial, nb, step, out, s);
+}
+
+#define PCLB_INST(R)                                                                               \
+  template hipError_t launch_models_ghost<R>(const Tables&, int, const BCdev&, const void*, void*, \
+                                             hipStream_t);                                         \
+  template hipError_t launch_models_step<R>(const Tables&, int, const void*, void*, const void*,   \
+                                            hipStream_t);                                          \
+  template hipError_t launch_models_init<R>(const Tables&, int, const double*, const double*,      \
+                                            const double*, const double*, void*, int*, hipStream_t); \
+  template hipError_t launch_models_fields<R>(const Tables&, int, const void*, double*, double*,   \
+                                              double*, double*, hipStream_t);                      \
+  template hipError_t launch_models_diag<R>(const Tables&, int, const void*, double*, double,      \
+                                            double*, hipStream_t);
+PCLB_INST(float)
+PCLB_INST(double)
+#undef PCLB_INST
+
+}  // namespace pclb

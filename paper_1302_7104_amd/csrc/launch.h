@@ -39,6 +39,26 @@ template <class R>
 hipError_t launch_noneq(const Tables& T, const void* f, int kinds, double* out, hipStream_t s);
 int diag_blocks();
 int diag_slots();
+hipError_t launch_diag_final(const double* partial, int nb, double step, double* out, hipStream_t s);
+
+// The double and triple octagon (n_i = 16 or 24 directions per speed): ghost
+// layers of 1 + 4 n_i planes, the per-node step of every scheme, initial
+// state, fields and diagnostics.
+template <class R>
+hipError_t launch_models_ghost(const Tables& T, int ni, const BCdev& bc, const void* f, void* ghost,
+                               hipStream_t s);
+template <class R>
+hipError_t launch_models_step(const Tables& T, int ni, const void* f, void* out, const void* ghost,
+                              hipStream_t s);
+template <class R>
+hipError_t launch_models_init(const Tables& T, int ni, const double* rho, const double* ur,
+                              const double* ut, const double* Tt, void* f, int* bad, hipStream_t s);
+template <class R>
+hipError_t launch_models_fields(const Tables& T, int ni, const void* f, double* rho, double* ur,
+                                double* ut, double* Tt, hipStream_t s);
+template <class R>
+hipError_t launch_models_diag(const Tables& T, int ni, const void* f, double* partial, double step,
+                              double* out, hipStream_t s);
 
 // Adjoint.
 template <class R>

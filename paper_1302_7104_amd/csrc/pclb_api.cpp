@@ -14,8 +14,8 @@
 
 using namespace pclb;
 
-// Scratch of pclb_step_static: the radial ghost layers (4 * 33 * n_theta
-// elements of the state type) in a file-scope device array, so that the entry
+// Scratch of pclb_step_static: the radial ghost layers (4 * (1 + 4 n_i) *
+// n_theta elements of the state type) in a file-scope device array, so that the entry
 // point needs no allocation.  Every GPU the library runs on holds its own copy
 // until the process ends; host code reaches it only through the per-device
 // address hipGetSymbolAddress returns (the array's name is a host-side
@@ -38,7 +38,7 @@ struct pclb_ctx {
   double tie = 0;               // adjoint tie threshold
   // context-owned device memory
   double* d_geom = nullptr;     // cth[nth], sth[nth], rinv[nr], wA[nr]
-  void* d_ghost = nullptr;      // 4 * 33 * nth elements of the state type
+  void* d_ghost = nullptr;      // 4 * nq * nth elements of the state type, nq = 1 + 4 n_i
   double* d_partial = nullptr;  // diagnostics partials
   double* d_diag = nullptr;     // 8 doubles for the synchronizing variant
   int* d_flag = nullptr;        // init validation flag
@@ -65,8 +65,12 @@ int hip_fail(pclb_ctx* c, hipError_t e, const char* where) {
   return fail(c, PCLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// theta increment of Sec. II.C: 2 pi n_f / (n_i n_theta) with n_i = 8
-double sector_dth(const pclb_config* c) { return 2.0 * PI * c->n_f / (8.0 * c->n_theta); }
+// velocities of the model: the rest velocity and n_i directions per speed
+int model_nq(int ni) { return 1 + NK * ni; }
+bool model_ok(int ni) { return ni == 8 || ni == 16 || ni == 24; }
+
+// theta increment of Sec. II.C: 2 pi n_f / (n_i n_theta)
+double sector_dth(const pclb_config* c) { return 2.0 * PI * c->n_f / ((double)c->n_i * c->n_theta); }
 
 int validate(const pclb_config* c, std::string& why) {
   if (!c) { why = "null config"; return PCLB_EINVAL; }
@@ -76,8 +80,8 @@ int validate(const pclb_config* c, std::string& why) {
   if ((int64_t)c->n_r * c->n_theta > (int64_t)1 << 31) { why = "grid too large"; return PCLB_EINVAL; }
   if (!(c->tau > 0.0) || !std::isfinite(c->tau)) { why = "tau must be > 0"; return PCLB_EINVAL; }
   if (!(c->dt > 0.0) || !std::isfinite(c->dt)) { why = "dt must be > 0"; return PCLB_EINVAL; }
-  if (c->n_i != 8) { why = "only the octagon model (n_i = 8) is built"; return PCLB_EINVAL; }
-  if (c->n_f < 1 || c->n_f > 8) { why = "n_f must be in 1..8 (theta covers 2 pi n_f / 8)"; return PCLB_EINVAL; }
+  if (!model_ok(c->n_i)) { why = "n_i must be 8, 16 or 24 (Table I)"; return PCLB_EINVAL; }
+  if (c->n_f < 1 || c->n_f > c->n_i) { why = "n_f must be in 1..n_i (theta covers 2 pi n_f / n_i)"; return PCLB_EINVAL; }
   if (c->precision != 32 && c->precision != 64) { why = "precision must be 32 or 64"; return PCLB_EINVAL; }
   if (c->fp64_collision != 1) {
     why = "fp64_collision must be 1 (float collision is not offered: it loses accuracy and no time)";
@@ -112,6 +116,11 @@ int validate(const pclb_config* c, std::string& why) {
 
 template <class R>
 hipError_t do_step(pclb_ctx* c, const void* in, void* out, void* ghost) {
+  if (c->cfg.n_i != 8) {
+    hipError_t e = launch_models_ghost<R>(c->T, c->cfg.n_i, c->bc, in, ghost, c->stream);
+    if (e != hipSuccess) return e;
+    return launch_models_step<R>(c->T, c->cfg.n_i, in, out, ghost, c->stream);
+  }
   hipError_t e = launch_ghost<R>(c->T, c->bc, in, ghost, c->stream);
   if (e != hipSuccess) return e;
   int kern = c->cfg.kernel;
@@ -126,7 +135,7 @@ hipError_t step_once(pclb_ctx* c, const void* in, void* out, void* ghost) {
                                 : do_step<double>(c, in, out, ghost);
 }
 
-size_t ghost_bytes(const pclb_ctx* c) { return 4 * (size_t)NQ * c->cfg.n_theta * elem_size(c); }
+size_t ghost_bytes(const pclb_ctx* c) { return 4 * (size_t)model_nq(c->cfg.n_i) * c->cfg.n_theta * elem_size(c); }
 
 }  // namespace
 
@@ -134,7 +143,7 @@ extern "C" {
 
 double pclb_cfl_dt(const pclb_config* cfg, double cfl) {
   if (!cfg || !(cfg->r1 > 0) || !(cfg->r2 > cfg->r1) || cfg->n_r < 2 || cfg->n_theta < 1 ||
-      cfg->n_f < 1 || cfg->n_f > 8 || !(cfl > 0))
+      !model_ok(cfg->n_i) || cfg->n_f < 1 || cfg->n_f > cfg->n_i || !(cfl > 0))
     return -1.0;
   double dr = (cfg->r2 - cfg->r1) / (cfg->n_r - 1);
   double dth = sector_dth(cfg);
@@ -184,7 +193,7 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   }
   size_t es = cfg->precision == 32 ? 4 : 8;
   bool ok = hipMalloc(&c->d_geom, ngeom * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->d_ghost, 4 * (size_t)NQ * nth * es) == hipSuccess &&
+            hipMalloc(&c->d_ghost, 4 * (size_t)model_nq(cfg->n_i) * nth * es) == hipSuccess &&
             hipMalloc(&c->d_partial, (size_t)diag_blocks() * diag_slots() * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->d_diag, 8 * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->d_flag, sizeof(int)) == hipSuccess &&
@@ -213,7 +222,7 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
   T.sth = c->d_geom + nth;
   T.rinv = c->d_geom + 2 * nth;
   T.wA = c->d_geom + 2 * nth + nr;
-  T.n_mixed = strip_mixed_count(nth, cfg->n_f);
+  T.n_mixed = cfg->n_i == 8 ? strip_mixed_count(nth, cfg->n_f) : 0;
   for (int s = 0; s < 2; ++s) {
     c->bc.kind[s] = PCLB_WALL;
     c->bc.neq[s] = 0;
@@ -281,9 +290,15 @@ int pclb_init_state(pclb_ctx* c, const double* rho, const double* ur, const doub
   if (!rho || !ur || !ut || !T) return fail(c, PCLB_EINVAL, "null field pointer");
   hipError_t e = launch_zero_int(c->d_flag, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "flag reset");
-  e = c->cfg.precision == 32
-          ? launch_init<float>(c->T, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream)
-          : launch_init<double>(c->T, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream);
+  const int ni = c->cfg.n_i;
+  if (ni != 8)
+    e = c->cfg.precision == 32
+            ? launch_models_init<float>(c->T, ni, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream)
+            : launch_models_init<double>(c->T, ni, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream);
+  else
+    e = c->cfg.precision == 32
+            ? launch_init<float>(c->T, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream)
+            : launch_init<double>(c->T, rho, ur, ut, T, c->f[c->cur], c->d_flag, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "init launch");
   int flag = 0;
   e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -315,8 +330,8 @@ int pclb_step_static(pclb_ctx* c, int64_t n) {
     char buf[200];
     std::snprintf(buf, sizeof buf,
                   "ghost layers need %zu bytes, above the %zu-byte static scratch (n_theta <= %zu "
-                  "at this precision)",
-                  ghost_bytes(c), STATIC_SCRATCH_BYTES, STATIC_SCRATCH_BYTES / (4 * NQ * elem_size(c)));
+                  "at this precision and n_i)",
+                  ghost_bytes(c), STATIC_SCRATCH_BYTES, STATIC_SCRATCH_BYTES / (4 * model_nq(c->cfg.n_i) * elem_size(c)));
     return fail(c, PCLB_EINVAL, buf);
   }
   for (int64_t s = 0; s < n; ++s) {
@@ -353,13 +368,25 @@ int pclb_moments_of(pclb_ctx* c, const void* f, double* rho, double* ur, double*
   if (!c) return PCLB_EINVAL;
   if (!f) return fail(c, PCLB_EINVAL, "null state buffer");
   hipError_t e = hipSuccess;
-  if (rho || ur || ut || T)
-    e = c->cfg.precision == 32 ? launch_fields<float>(c->T, f, rho, ur, ut, T, c->stream)
-                               : launch_fields<double>(c->T, f, rho, ur, ut, T, c->stream);
+  const int ni = c->cfg.n_i;
+  const bool f32 = c->cfg.precision == 32;
+  if (rho || ur || ut || T) {
+    if (ni != 8)
+      e = f32 ? launch_models_fields<float>(c->T, ni, f, rho, ur, ut, T, c->stream)
+              : launch_models_fields<double>(c->T, ni, f, rho, ur, ut, T, c->stream);
+    else
+      e = f32 ? launch_fields<float>(c->T, f, rho, ur, ut, T, c->stream)
+              : launch_fields<double>(c->T, f, rho, ur, ut, T, c->stream);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "fields launch");
   if (diag8) {
-    e = c->cfg.precision == 32 ? launch_diag<float>(c->T, f, c->d_partial, (double)c->steps, diag8, c->stream)
-                               : launch_diag<double>(c->T, f, c->d_partial, (double)c->steps, diag8, c->stream);
+    const double step = (double)c->steps;
+    if (ni != 8)
+      e = f32 ? launch_models_diag<float>(c->T, ni, f, c->d_partial, step, diag8, c->stream)
+              : launch_models_diag<double>(c->T, ni, f, c->d_partial, step, diag8, c->stream);
+    else
+      e = f32 ? launch_diag<float>(c->T, f, c->d_partial, step, diag8, c->stream)
+              : launch_diag<double>(c->T, f, c->d_partial, step, diag8, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
   }
   return PCLB_OK;
@@ -387,6 +414,7 @@ int pclb_noneq(pclb_ctx* c, const void* f, int32_t kinds, double* out) {
   if (!c) return PCLB_EINVAL;
   if (kinds <= 0 || kinds > PCLB_NONEQ_ALL) return fail(c, PCLB_EINVAL, "kinds must be a nonzero mask of PCLB_NONEQ_*");
   if (!out) return fail(c, PCLB_EINVAL, "null output");
+  if (c->cfg.n_i != 8) return fail(c, PCLB_EINVAL, "non-equilibrium moments are built for the octagon (n_i = 8) only");
   if (!f) {
     if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
     f = c->f[c->cur];
@@ -402,6 +430,7 @@ int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* 
   if (!f_t || !lam_next || !lam_out || lam_out == lam_next || lam_out == f_t)
     return fail(c, PCLB_EINVAL, "three non-null buffers, lam_out distinct from the inputs");
   if (c->cfg.scheme != PCLB_SCHEME_MWB) return fail(c, PCLB_EINVAL, "the adjoint covers the MWB scheme only");
+  if (c->cfg.n_i != 8) return fail(c, PCLB_EINVAL, "the adjoint covers the octagon (n_i = 8) only");
   if (c->bc.neq[0] || c->bc.neq[1])
     return fail(c, PCLB_EINVAL, "the adjoint covers equilibrium ghost layers only (no PCLB_BC_NONEQ)");
   hipError_t e = c->cfg.precision == 32
@@ -417,6 +446,7 @@ int pclb_adjoint_init(pclb_ctx* c, const void* lam0, const double* rho, const do
   if (!c) return PCLB_EINVAL;
   if (!lam0 || !rho || !ur || !ut || !T || !d_rho || !d_ur || !d_ut || !d_T)
     return fail(c, PCLB_EINVAL, "null pointer");
+  if (c->cfg.n_i != 8) return fail(c, PCLB_EINVAL, "the adjoint covers the octagon (n_i = 8) only");
   hipError_t e = c->cfg.precision == 32
                      ? launch_adjoint_init<float>(c->T, lam0, rho, ur, ut, T, d_rho, d_ur, d_ut, d_T, c->stream)
                      : launch_adjoint_init<double>(c->T, lam0, rho, ur, ut, T, d_rho, d_ur, d_ut, d_T, c->stream);

@@ -15,7 +15,7 @@ import torch
 
 from . import _native as N
 
-NQ = 33
+NQ = 33   # velocities of the octagon; the double and triple octagon have 65 and 97
 
 
 def _ptr(t: torch.Tensor | None):
@@ -26,7 +26,8 @@ class Sim:
     """One annulus, one precision, one device.
 
     ``problem`` is any object with nr, nth, r1, r2, tau, dt, bc_kind, bc_par
-    and optionally nf (e.g. a ``workloads.Problem``).  ``strip_*`` set the
+    and optionally nf and ni (e.g. a ``workloads.Problem``; ni = 8, 16 or 24
+    directions per speed, the state then holds 1 + 4 ni velocity planes).  ``strip_*`` set the
     launch shape of the strip kernel (0: default), ``adjoint_tie`` the tie
     threshold of the adjoint (0: the precision's default), ``scheme`` and
     ``relaxation`` the convection scheme and the relaxation form (the
@@ -47,13 +48,15 @@ class Sim:
         self.precision = precision
         self.dtype = torch.float32 if precision == 32 else torch.float64
         self.nr, self.nth = problem.nr, problem.nth
+        self.ni = int(getattr(problem, "ni", 8))
+        self.nq = 1 + 4 * self.ni
         self.cfg = N.Config(problem.nr, problem.nth, problem.r1, problem.r2, problem.tau,
-                            problem.dt, 8, getattr(problem, "nf", 8), precision, 1, kernel,
+                            problem.dt, self.ni, getattr(problem, "nf", 8), precision, 1, kernel,
                             strip_chunk, strip_order, adjoint_tie, scheme, relaxation)
         ctx = ctypes.c_void_p()
         N.check(self.L.pclb_create(ctypes.byref(self.cfg), ctypes.byref(ctx)), None)
         self.ctx = ctx
-        shape = (NQ, self.nr, self.nth)
+        shape = (self.nq, self.nr, self.nth)
         self.buf = [torch.empty(shape, dtype=self.dtype, device=self.device),
                     torch.empty(shape, dtype=self.dtype, device=self.device)]
         self.stream = torch.cuda.current_stream(self.device)
@@ -124,9 +127,9 @@ class Sim:
         N.check(self.L.pclb_step_into(self.ctx, _ptr(f_in), _ptr(f_out)), self.ctx)
 
     def _check_state_tensor(self, t: torch.Tensor):
-        if t.dtype != self.dtype or t.shape != (NQ, self.nr, self.nth) or not t.is_contiguous() \
+        if t.dtype != self.dtype or t.shape != (self.nq, self.nr, self.nth) or not t.is_contiguous() \
                 or t.device != self.device:
-            raise ValueError("state tensors must be contiguous (33, nr, nth) of the context dtype")
+            raise ValueError(f"state tensors must be contiguous ({self.nq}, nr, nth) of the context dtype")
 
     # -- diagnostics -------------------------------------------------------
     def fields(self, f: torch.Tensor | None = None):

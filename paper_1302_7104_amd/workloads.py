@@ -61,7 +61,8 @@ class Problem:
     bc_kind: tuple = (WALL, WALL)
     bc_par: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
     params: dict = field(default_factory=dict, compare=False, hash=False)
-    nf: int = 8          # theta covers 0 < theta <= 2 pi nf / 8 (8: the full annulus)
+    nf: int = 8          # theta covers 0 < theta <= 2 pi nf / ni (nf = ni: the full annulus)
+    ni: int = 8          # directions per speed: 8 octagon, 16 double, 24 triple octagon (Table I)
 
     @property
     def dr(self) -> float:
@@ -69,25 +70,26 @@ class Problem:
 
     @property
     def dth(self) -> float:
-        return 2.0 * math.pi * self.nf / (8.0 * self.nth)
+        return 2.0 * math.pi * self.nf / (self.ni * self.nth)
 
     @property
     def nodes(self) -> int:
         return self.nr * self.nth
 
 
-def cfl_dt(nr: int, nth: int, r1: float, r2: float, cfl: float = 0.3, nf: int = 8) -> float:
+def cfl_dt(nr: int, nth: int, r1: float, r2: float, cfl: float = 0.3, nf: int = 8,
+           ni: int = 8) -> float:
     """dt = cfl * min(dr, R1 dtheta) / max|v| (the configs' time-step rule)."""
     dr = (r2 - r1) / (nr - 1)
-    dth = 2.0 * math.pi * nf / (8.0 * nth)
+    dth = 2.0 * math.pi * nf / (ni * nth)
     return cfl * min(dr, r1 * dth) / MAX_SPEED
 
 
-def node_coords(nr: int, nth: int, r1: float, r2: float, nf: int = 8):
-    """r_i = R1 + i dr, theta_j = (j+1) dtheta with dtheta = 2 pi nf / (8 nth)
+def node_coords(nr: int, nth: int, r1: float, r2: float, nf: int = 8, ni: int = 8):
+    """r_i = R1 + i dr, theta_j = (j+1) dtheta with dtheta = 2 pi nf / (ni nth)
     (Sec. II.C node placement, 0-based); returns 2-D arrays R[i, j], TH[i, j]."""
     dr = (r2 - r1) / (nr - 1)
-    dth = 2.0 * math.pi * nf / (8.0 * nth)
+    dth = 2.0 * math.pi * nf / (ni * nth)
     r = r1 + dr * np.arange(nr, dtype=np.float64)
     th = dth * (np.arange(nth, dtype=np.float64) + 1.0)
     return np.meshgrid(r, th, indexing="ij")
@@ -266,16 +268,17 @@ def uniform(nr, nth, r1=1.0, r2=2.0, rho=1.0, ux=0.0, uy=0.0, T=1.0, tau=1e-3,
 
 
 def smooth_random(nr, nth, r1=1.0, r2=2.0, tau=2e-3, seed=0, amp=0.05, cfl=0.3,
-                  bc=(WALL, WALL), bc_par=((0.1, 0, 0, 0), (-0.05, 0, 0, 0)), nf=8):
+                  bc=(WALL, WALL), bc_par=((0.1, 0, 0, 0), (-0.05, 0, 0, 0)), nf=8, ni=8):
     """Smooth seeded fields: a few low azimuthal/radial modes around rho = 1,
-    T = 1, u = 0, with relative amplitude ``amp``; on a sector (nf < 8) the
-    azimuthal modes are periodic over the sector."""
+    T = 1, u = 0, with relative amplitude ``amp``; on a sector (nf < ni) the
+    azimuthal modes are periodic over the sector.  ni picks the velocity model
+    (8, 16 or 24 directions per speed)."""
     rng = np.random.default_rng(seed)
-    dt = cfl_dt(nr, nth, r1, r2, cfl, nf)
-    P = Problem("smooth_random", nr, nth, r1, r2, tau, dt, 0, bc, bc_par, {"seed": seed}, nf)
-    R, TH = node_coords(nr, nth, r1, r2, nf)
+    dt = cfl_dt(nr, nth, r1, r2, cfl, nf, ni)
+    P = Problem("smooth_random", nr, nth, r1, r2, tau, dt, 0, bc, bc_par, {"seed": seed}, nf, ni)
+    R, TH = node_coords(nr, nth, r1, r2, nf, ni)
     x = (R - r1) / (r2 - r1)
-    period = 8.0 / nf
+    period = float(ni) / nf
 
     def modes(scale):
         out = np.zeros_like(R)

@@ -46,12 +46,18 @@ def test_cfl_dt_matches_workload_rule():
     dt1 = N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_f=1, n_theta=20)), 0.3)
     assert abs(dt1 - W.cfl_dt(64, 20, 1.0, 2.0, 0.3, nf=1)) < 1e-18
     assert N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_f=0)), 0.3) < 0
+    # the double and triple octagon: dtheta = 2 pi n_f / (n_i n_theta)
+    for ni, nf in ((16, 16), (16, 3), (24, 24), (24, 7)):
+        d = N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_i=ni, n_f=nf, n_theta=40)), 0.3)
+        assert abs(d - W.cfl_dt(64, 40, 1.0, 2.0, 0.3, nf=nf, ni=ni)) < 1e-18, (ni, nf)
+    assert N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_i=16, n_f=17)), 0.3) < 0
+    assert N.lib().pclb_cfl_dt(ctypes.byref(cfg(n_i=12, n_f=8)), 0.3) < 0
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(r1=0.0), -1), (dict(r2=0.5), -1), (dict(n_r=3), -1), (dict(n_theta=4), -1),
-    (dict(tau=0.0), -1), (dict(dt=-1.0), -1), (dict(n_i=16), -1), (dict(n_f=0), -1),
-    (dict(n_f=9), -1), (dict(n_f=1, dt=2e-3), -2),
+    (dict(tau=0.0), -1), (dict(dt=-1.0), -1), (dict(n_i=12), -1), (dict(n_i=32), -1),
+    (dict(n_f=0), -1), (dict(n_f=9), -1), (dict(n_i=16, n_f=17), -1), (dict(n_i=24, n_f=25), -1), (dict(n_f=1, dt=2e-3), -2),
     (dict(precision=16), -1), (dict(kernel=7), -1), (dict(dt=0.01), -2),
     (dict(fp64_collision=0), -1), (dict(adjoint_tie=-1.0), -1), (dict(adjoint_tie=0.5), -1),
     (dict(scheme=4), -1), (dict(scheme=-1), -1), (dict(relaxation=2), -1),
