@@ -256,23 +256,40 @@ __global__ void __launch_bounds__(DIAG_BLOCK) diag_partial_kernel(Tables T, cons
   diag_block_reduce(acc, rmin, tmin, bad, partial);
 }
 
+// Final pass: one wavefront.  Lane l merges the partial rows l, l + 64,
+// l + 128, ... in that order, then the lanes' results meet in a butterfly of
+// fixed shape (offsets 32, 16, ..., 1), so the sums are the same on every run.
 __global__ void __launch_bounds__(64) diag_final_kernel(const double* __restrict__ partial, int nb,
                                                         double step, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+  const int lane = threadIdx.x;
   TwoS acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   double rmin = INFINITY, tmin = INFINITY, bad = 0.0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = lane; b < nb; b += 64) {
     const double* p = partial + (size_t)b * DIAG_SLOTS;
     for (int a = 0; a < 4; ++a) acc[a] = two_merge(acc[a], TwoS{p[2 * a], p[2 * a + 1]});
     rmin = fmin(rmin, p[8]);
     tmin = fmin(tmin, p[9]);
     bad += p[10];
   }
-  for (int a = 0; a < 4; ++a) out[a] = acc[a].s + acc[a].c;
-  out[4] = rmin;
-  out[5] = tmin;
-  out[6] = bad;
-  out[7] = step;
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int a = 0; a < 4; ++a) {
+      const TwoS other{__shfl_xor(acc[a].s, o), __shfl_xor(acc[a].c, o)};
+      // the lower lane of each pair keeps its own sum first, so both lanes
+      // of a pair form the same result
+      acc[a] = (lane & o) ? two_merge(other, acc[a]) : two_merge(acc[a], other);
+    }
+    rmin = fmin(rmin, __shfl_xor(rmin, o));
+    tmin = fmin(tmin, __shfl_xor(tmin, o));
+    const double ob = __shfl_xor(bad, o);
+    bad = (lane & o) ? ob + bad : bad + ob;
+  }
+  if (lane == 0) {
+    for (int a = 0; a < 4; ++a) out[a] = acc[a].s + acc[a].c;
+    out[4] = rmin;
+    out[5] = tmin;
+    out[6] = bad;
+    out[7] = step;
+  }
 }
 
 // ---------------------------------------------------------------------------

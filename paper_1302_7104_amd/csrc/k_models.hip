@@ -121,14 +121,13 @@ __device__ inline double row_weight(double E) {
 
 template <int NI> constexpr int nq_of() { return 1 + NK * NI; }
 
-// Equilibrium coefficients of one node (Eq. feq in the factorised form of the
-// octagon kernels): rho F_k and P(w) = A0 + A1 w + ... + A4 w^4, w = v . u.
-struct Eq {
-  double rF[NK + 1];
-  double A0, A1, A2, A3, A4, ux, uy;
-};
+// Equilibrium coefficients of one node in the octagon kernels' factorised
+// form (Eq. feq: f^eq = rho F_k P(w), P(w) = A0 + A1 w + ... + A4 w^4,
+// w = v_k u . e_d) with this model's weights; the relaxation of an opposite
+// pair (d, d + N_i/2) then goes through relax_pair, whose even and odd parts
+// of P serve both members.
 template <int NI>
-__device__ inline void eq_of(double rho, double ux, double uy, double E, Eq& c) {
+__device__ inline void eq_models(double rho, double ux, double uy, double E, EqCoef& c) {
   const double F1 = row_weight<NI, 0>(E), F2 = row_weight<NI, 1>(E);
   const double F3 = row_weight<NI, 2>(E), F4 = row_weight<NI, 3>(E);
   c.rF[1] = rho * F1;
@@ -143,46 +142,61 @@ __device__ inline void eq_of(double rho, double ux, double uy, double E, Eq& c) 
   c.A2 = 0.5 * g * iE2;
   c.A3 = iE2 * iE * (1.0 / 6.0);
   c.A4 = iE2 * iE2 * (1.0 / 24.0);
-  c.ux = ux;
-  c.uy = uy;
+  c.p[0] = ux;   // the Cartesian velocity (u . e_d is formed per direction)
+  c.p[1] = uy;
+  c.p[2] = c.p[3] = 0.0;
 }
-// f^eq of velocity (K, d); K = 0 is the rest velocity.
-template <int NI, int K>
-__device__ inline double feq_kd(const Eq& c, int d) {
-  if constexpr (K == 0) {
-    return c.rF[0] * c.A0;
-  } else {
-    const double w = speed(K) * (c.ux * dirs<NI>().c[d] + c.uy * dirs<NI>().s[d]);
-    return c.rF[K] * (c.A0 + w * (c.A1 + w * (c.A2 + w * (c.A3 + w * c.A4))));
+
+// f^eq of the pair (K, d) and (K, d + N_i/2), pd = u . e_d.
+template <int K>
+__device__ inline void feq_pair(const EqCoef& c, double pd, double& fp, double& fm) {
+  const double w = speed(K) * pd, w2 = w * w;
+  const double ev = c.A0 + w2 * (c.A2 + w2 * c.A4);
+  const double od = w * (c.A1 + w2 * c.A3);
+  fp = c.rF[K] * (ev + od);
+  fm = c.rF[K] * (ev - od);
+}
+
+// fn(k, d, qp, qm) for every opposite pair: speed group k as a compile-time
+// constant, direction d = 0 .. N_i/2 - 1 in a runtime loop (outer), planes qp
+// of (k, d) and qm of (k, d + N_i/2).  The direction's constants are loaded
+// once for its four speeds, and the eight velocities' loads of one iteration
+// are in flight together.
+template <int NI, class Fn>
+__device__ inline void for_each_pair(Fn&& fn) {
+#pragma unroll 1
+  for (int d = 0; d < NI / 2; ++d) {
+    for_k<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int qp = 1 + NI * (k - 1) + d;
+      fn(kc, d, qp, qp + NI / 2);
+    });
   }
 }
 
-// fn(k, d, q) for every moving velocity: the speed group k as a compile-time
-// constant (so that per-speed coefficients stay in registers), the direction
-// d in a runtime loop.
-template <int NI, class Fn>
-__device__ inline void for_each_moving(Fn&& fn) {
-  for_k<1>([&](auto kc) {
-#pragma unroll 1
-    for (int d = 0; d < NI; ++d) fn(kc, d, 1 + NI * (decltype(kc)::value - 1) + d);
-  });
-}
-
-// rho, u, E of one node (Eqs. moment1-moment3) from its values get(q).
+// rho, u, E of one node (Eqs. moment1-moment3) from its values get(q), summed
+// per opposite pair (sp = f_d + f_{d+N/2}, sm = f_d - f_{d+N/2}) with the
+// rest velocity last; jeps, if given, receives rho u_x, rho u_y and the
+// energy density sum f v^2 / 2.  fin becomes false if a value is not finite.
 template <int NI, class Get>
 __device__ inline void moments_of(Get get, double& rho, double& ux, double& uy, double& E,
-                                  double* jeps = nullptr) {
-  double r = get(0), jx = 0.0, jy = 0.0, eps = 0.0;
-  for_each_moving<NI>([&](auto kc, int d, int q) {
+                                  double* jeps = nullptr, bool* fin = nullptr) {
+  double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
+  bool ok = true;
+  for_each_pair<NI>([&](auto kc, int d, int qp, int qm) {
     constexpr int k = decltype(kc)::value;
-    const double x = get(q);
-    r += x;
-    jx += x * (speed(k) * dirs<NI>().c[d]);
-    jy += x * (speed(k) * dirs<NI>().s[d]);
-    eps += x * (speed(k) * speed(k));
+    const double a = get(qp), b = get(qm);
+    if (fin) ok = ok && isfinite(a) && isfinite(b);
+    const double sp = a + b, sm = a - b;
+    r += sp;
+    jx += (speed(k) * dirs<NI>().c[d]) * sm;
+    jy += (speed(k) * dirs<NI>().s[d]) * sm;
+    eps += (speed(k) * speed(k)) * sp;
   });
-  rho = r;
-  const double ir = 1.0 / r;
+  const double f0 = get(0);
+  if (fin) *fin = ok && isfinite(f0);
+  rho = r + f0;
+  const double ir = 1.0 / rho;
   ux = jx * ir;
   uy = jy * ir;
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
@@ -225,8 +239,8 @@ __global__ void __launch_bounds__(256) models_ghost_kernel(Tables T, BCdev bc, c
   moments_of<NI>([&](int q) { return (double)f1[q * plane]; }, m[1][0], m[1][1], m[1][2], m[1][3]);
   const double ct = T.cth[j], st = T.sth[j];
   const bool neq = bc.neq[side] != 0;
-  Eq c0{};
-  if (neq) eq_of<NI>(m[0][0], m[0][1], m[0][2], m[0][3], c0);
+  EqCoef c0{};
+  if (neq) eq_models<NI>(m[0][0], m[0][1], m[0][2], m[0][3], c0);
   double prev[4] = {m[0][0], m[0][1], m[0][2], m[0][3]};
   double pprev[4] = {m[1][0], m[1][1], m[1][2], m[1][3]};
   const int kind = bc.kind[side];
@@ -245,65 +259,102 @@ __global__ void __launch_bounds__(256) models_ghost_kernel(Tables T, BCdev bc, c
       uy = bc.p[side][1] * st + bc.p[side][2] * ct;
       E = bc.p[side][3];
     }                                  // EXTRAPOLATE keeps the extrapolated u
-    Eq c;
-    eq_of<NI>(rho, ux, uy, E, c);
-    const double nv0 = neq ? (double)f0[0] - feq_kd<NI, 0>(c0, 0) : 0.0;
-    ghost[gidx(side, layer, 0, j, T.nth, NQM)] = (R)(feq_kd<NI, 0>(c, 0) + nv0);
-    for_each_moving<NI>([&](auto kc, int d, int q) {
+    EqCoef c;
+    eq_models<NI>(rho, ux, uy, E, c);
+    const double nv0 = neq ? (double)f0[0] - c0.rF[0] * c0.A0 : 0.0;
+    ghost[gidx(side, layer, 0, j, T.nth, NQM)] = (R)(c.rF[0] * c.A0 + nv0);
+    for_each_pair<NI>([&](auto kc, int d, int qp, int qm) {
       constexpr int k = decltype(kc)::value;
-      const double nv = neq ? (double)f0[q * plane] - feq_kd<NI, k>(c0, d) : 0.0;
-      ghost[gidx(side, layer, q, j, T.nth, NQM)] = (R)(feq_kd<NI, k>(c, d) + nv);
+      const double cd = dirs<NI>().c[d], sd = dirs<NI>().s[d];
+      double ep, em, np = 0.0, nm = 0.0;
+      feq_pair<k>(c, ux * cd + uy * sd, ep, em);
+      if (neq) {
+        double wp, wm;
+        feq_pair<k>(c0, c0.p[0] * cd + c0.p[1] * sd, wp, wm);
+        np = (double)f0[qp * plane] - wp;
+        nm = (double)f0[qm * plane] - wm;
+      }
+      ghost[gidx(side, layer, qp, j, T.nth, NQM)] = (R)(ep + np);
+      ghost[gidx(side, layer, qm, j, T.nth, NQM)] = (R)(em + nm);
     });
   }
 }
 
-// Eq. combined_scheme for every velocity of node (i, j).
-template <class R, int NI, int SCH>
+// Eq. combined_scheme for every velocity of node (i, j): direction pairs
+// outer, speeds inner (the octagon node kernel's order).  The Courant factors
+// are formed as there: per direction |v_r| dt/dr and |v_theta| dt/dtheta per
+// unit speed rounded to the state type, then times 1/r and the speed.
+template <class R, int NI, int SCH, bool SECTOR>
 __global__ void __launch_bounds__(256) models_step_kernel(Tables T, const R* __restrict__ f,
                                                           R* __restrict__ out,
                                                           const R* __restrict__ ghost) {
-  constexpr int NQM = nq_of<NI>();
+  constexpr int NQM = nq_of<NI>(), NH = NI / 2;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   const int nr = T.nr, nth = T.nth;
   if (j >= nth) return;
   const size_t plane = (size_t)nr * nth;
-  const size_t c0 = (size_t)i * nth + j;
+  const size_t rowoff = (size_t)i * nth, c0 = rowoff + j;
   double rho, ux, uy, E;
   moments_of<NI>([&](int q) { return (double)f[q * plane + c0]; }, rho, ux, uy, E);
-  Eq ec;
-  eq_of<NI>(rho, ux, uy, E, ec);
+  EqCoef ec;
+  eq_models<NI>(rho, ux, uy, E, ec);
   const double e = T.e, ome = 1.0 - T.e;
   const double ct = T.cth[j], st = T.sth[j];
-  const double rinv = T.rinv[i];
+  const R rinv = (R)T.rinv[i];
+  // azimuthal neighbour columns, wrapped around the ring; on a sector a
+  // wrapped column reads the direction rotated by n_f (low end) or back
+  // (high end)
+  const int jm1 = j >= 1 ? j - 1 : j - 1 + nth, jm2 = j >= 2 ? j - 2 : j - 2 + nth;
+  const int jp1 = j + 1 < nth ? j + 1 : j + 1 - nth, jp2 = j + 2 < nth ? j + 2 : j + 2 - nth;
   const int s_lo = T.nf % NI, s_hi = (NI - T.nf % NI) % NI;
-  // value of velocity q at (ii, jj): radial ghost rows below 0 and above
-  // nr - 1, azimuthal wrap with the sector's direction rotation
-  auto value = [&](int q, int ii, int jj) -> R {
-    if (jj < 0) return f[rotq<NI>(q, s_lo) * plane + (size_t)ii * nth + (jj + nth)];
-    if (jj >= nth) return f[rotq<NI>(q, s_hi) * plane + (size_t)ii * nth + (jj - nth)];
-    if (ii < 0) return ghost[gidx(0, -1 - ii, q, jj, nth, NQM)];
-    if (ii >= nr) return ghost[gidx(1, ii - nr, q, jj, nth, NQM)];
-    return f[q * plane + (size_t)ii * nth + jj];
+  const int rm1 = j >= 1 ? 0 : s_lo, rm2 = j >= 2 ? 0 : s_lo;
+  const int rp1 = j + 1 < nth ? 0 : s_hi, rp2 = j + 2 < nth ? 0 : s_hi;
+  auto azi = [&](int q, int dj) -> R {
+    const int t = dj == -1 ? jm1 : dj == -2 ? jm2 : dj == 1 ? jp1 : jp2;
+    int qq = q;
+    if constexpr (SECTOR) qq = rotq<NI>(q, dj == -1 ? rm1 : dj == -2 ? rm2 : dj == 1 ? rp1 : rp2);
+    return f[qq * plane + rowoff + t];
   };
-  out[c0] = (R)fma((double)f[c0], e, ome * feq_kd<NI, 0>(ec, 0));   // rest velocity: no convection
-  for_each_moving<NI>([&](auto kc, int d, int q) {
-    constexpr int k = decltype(kc)::value;
-    const double cd = dirs<NI>().c[d], sd = dirs<NI>().s[d];
-    const double fq = (double)f[q * plane + c0];
-    const double rel = fma(fq, e, ome * feq_kd<NI, k>(ec, d));
-    const double vr = speed(k) * (cd * ct + sd * st), vt = speed(k) * (sd * ct - cd * st);
-    const R aCr = (R)(fabs(vr) * T.dt_dr), aCt = (R)(fabs(vt) * T.dt_dth * rinv);
-    const R Kr = aCr - aCr * aCr, Kt = aCt - aCt * aCt;
-    const int sr = vr >= 0.0 ? -1 : 1, sc = vt >= 0.0 ? -1 : 1;   // upwind offsets
-    const R c = (R)fq;
-    // the downwind neighbours only matter to Lax-Wendroff
-    const R wr = SCH == SCH_LW ? value(q, i - sr, j) : c;
-    const R wt = SCH == SCH_LW ? value(q, i, j - sc) : c;
-    const R tr = conv_term<SCH, R>(aCr, Kr, c, value(q, i + sr, j), value(q, i + 2 * sr, j), wr);
-    const R tt = conv_term<SCH, R>(aCt, Kt, c, value(q, i, j + sc), value(q, i, j + 2 * sc), wt);
+  auto rad = [&](int q, int di) -> R {
+    const int ii = i + di;
+    if (ii < 0) return ghost[gidx(0, -1 - ii, q, j, nth, NQM)];
+    if (ii >= nr) return ghost[gidx(1, ii - nr, q, j, nth, NQM)];
+    return f[q * plane + c0 + (ptrdiff_t)di * nth];
+  };
+  out[c0] = relax_rest<R>(relax_rest_share(ec, ome), e, (double)f[c0]);   // rest velocity: no convection
+  // update of one velocity q with centre value c, relaxed value rel, upwind
+  // offsets sr, sc and Courant factors
+  auto update = [&](int q, R c, double rel, int sr, int sc, R aCr, R Kr, R aCt, R Kt) {
+    const R wr = SCH == SCH_LW ? rad(q, -sr) : c;   // downwind: Lax-Wendroff only
+    const R wt = SCH == SCH_LW ? azi(q, -sc) : c;
+    const R tr = conv_term<SCH, R>(aCr, Kr, c, rad(q, sr), rad(q, 2 * sr), wr);
+    const R tt = conv_term<SCH, R>(aCt, Kt, c, azi(q, sc), azi(q, 2 * sc), wt);
     out[q * plane + c0] = (R)((rel - (double)tr) - (double)tt);
-  });
+  };
+#pragma unroll 1
+  for (int d = 0; d < NH; ++d) {
+    const double cd = dirs<NI>().c[d], sd = dirs<NI>().s[d];
+    const double pd = ux * cd + uy * sd;
+    const double vr = cd * ct + sd * st, vt = sd * ct - cd * st;   // per unit speed
+    const R ar = (R)(fabs(vr) * T.dt_dr), at = (R)(fabs(vt) * T.dt_dth) * rinv;
+    // upwind sides: backward (stencil at lower index) where the component is
+    // >= 0; the opposite direction has the negated components
+    const int srp = vr >= 0.0 ? -1 : 1, scp = vt >= 0.0 ? -1 : 1;
+    const int srm = -vr >= 0.0 ? -1 : 1, scm = -vt >= 0.0 ? -1 : 1;
+    for_k<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int qp = 1 + NI * (k - 1) + d, qm = qp + NH;
+      const R cp = f[qp * plane + c0], cm = f[qm * plane + c0];
+      double rp, rm;
+      relax_pair<k>(ec, e, ome, pd, (double)cp, (double)cm, rp, rm);
+      R aCr, Kr, aCt, Kt;
+      courant<R>((R)speed(k), ar, aCr, Kr);
+      courant<R>((R)speed(k), at, aCt, Kt);
+      update(qp, cp, rp, srp, scp, aCr, Kr, aCt, Kt);
+      update(qm, cm, rm, srm, scm, aCr, Kr, aCt, Kt);
+    });
+  }
 }
 
 // f = f^eq(rho, u, T), u given in polar components (Eq. feq).
@@ -322,11 +373,15 @@ __global__ void __launch_bounds__(256) models_init_kernel(Tables T, const double
   if (!(r > 0.0) || !(E > 0.0) || !isfinite(r) || !isfinite(E) || !isfinite(a) || !isfinite(b))
     atomicOr(bad, 1);
   const double ct = T.cth[j], st = T.sth[j];
-  Eq c;
-  eq_of<NI>(r, a * ct - b * st, a * st + b * ct, E, c);
-  f[c0] = (R)feq_kd<NI, 0>(c, 0);
-  for_each_moving<NI>([&](auto kc, int d, int q) {
-    f[q * plane + c0] = (R)feq_kd<NI, decltype(kc)::value>(c, d);
+  const double ux = a * ct - b * st, uy = a * st + b * ct;
+  EqCoef c;
+  eq_models<NI>(r, ux, uy, E, c);
+  f[c0] = (R)(c.rF[0] * c.A0);
+  for_each_pair<NI>([&](auto kc, int d, int qp, int qm) {
+    double ep, em;
+    feq_pair<decltype(kc)::value>(c, ux * dirs<NI>().c[d] + uy * dirs<NI>().s[d], ep, em);
+    f[qp * plane + c0] = (R)ep;
+    f[qm * plane + c0] = (R)em;
   });
 }
 
@@ -361,12 +416,10 @@ __global__ void __launch_bounds__(DIAG_BLOCK) models_diag_kernel(Tables T, const
   for (size_t n = (size_t)blockIdx.x * DIAG_BLOCK + threadIdx.x; n < plane;
        n += (size_t)gridDim.x * DIAG_BLOCK) {
     const int i = (int)(n / T.nth);
-    bool fin = true;
-#pragma unroll 1
-    for (int q = 0; q < nq_of<NI>(); ++q) fin = fin && isfinite((double)f[q * plane + n]);
-    if (!fin) { bad += 1.0; continue; }
     double rho, ux, uy, E, je[3];
-    moments_of<NI>([&](int q) { return (double)f[q * plane + n]; }, rho, ux, uy, E, je);
+    bool fin;
+    moments_of<NI>([&](int q) { return (double)f[q * plane + n]; }, rho, ux, uy, E, je, &fin);
+    if (!fin) { bad += 1.0; continue; }
     const double w = T.wA[i];
     two_add(acc[0], rho * w);
     two_add(acc[1], je[0] * w);
@@ -391,15 +444,21 @@ hipError_t launch_models_ghost(const Tables& T, int ni, const BCdev& bc, const v
   return hipGetLastError();
 }
 
+template <class R, int NI, int SCH>
+void launch_models_step_sch(const Tables& T, dim3 grid, const R* f, R* out, const R* gh, hipStream_t s) {
+  if (T.nf == NI)
+    hipLaunchKernelGGL((models_step_kernel<R, NI, SCH, false>), grid, dim3(256), 0, s, T, f, out, gh);
+  else
+    hipLaunchKernelGGL((models_step_kernel<R, NI, SCH, true>), grid, dim3(256), 0, s, T, f, out, gh);
+}
+
 template <class R, int NI>
 void launch_models_step_ni(const Tables& T, dim3 grid, const R* f, R* out, const R* gh, hipStream_t s) {
   switch (T.scheme) {
-    case SCH_WB: hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_WB>), grid, dim3(256), 0, s, T, f, out, gh); break;
-    case SCH_LW: hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_LW>), grid, dim3(256), 0, s, T, f, out, gh); break;
-    case SCH_UPWIND2:
-      hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_UPWIND2>), grid, dim3(256), 0, s, T, f, out, gh);
-      break;
-    default: hipLaunchKernelGGL((models_step_kernel<R, NI, SCH_MWB>), grid, dim3(256), 0, s, T, f, out, gh);
+    case SCH_WB: launch_models_step_sch<R, NI, SCH_WB>(T, grid, f, out, gh, s); break;
+    case SCH_LW: launch_models_step_sch<R, NI, SCH_LW>(T, grid, f, out, gh, s); break;
+    case SCH_UPWIND2: launch_models_step_sch<R, NI, SCH_UPWIND2>(T, grid, f, out, gh, s); break;
+    default: launch_models_step_sch<R, NI, SCH_MWB>(T, grid, f, out, gh, s);
   }
 }
 
