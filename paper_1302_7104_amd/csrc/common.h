@@ -322,16 +322,28 @@ PCLB_HD inline void courant(R vk, R a, R& aC, R& K) {
 // which equals [C + C(1-|C|)(1-S(eta))(1-eta)/2] delta for either sign of C,
 // and whose limiter part is 0 when d1 = d2 = 0.
 //
-// Limiter part (d1 - d2) |d1| / (|d1| + |d2|).  Double: a guarded IEEE
-// division.  Float on the device: the weight |d1| / (|d1| + |d2|) from the
-// hardware reciprocal, saturated to [0, 1] by the VALU clamp, which also sends
-// the 0 * inf of d1 = d2 = 0 to 0.
+// Limiter part (d1 - d2) |d1| / (|d1| + |d2|).  Double on the device: the
+// weight |d1| / (|d1| + |d2|) from the hardware reciprocal refined by two
+// Newton steps (within an ulp or two of the quotient; the IEEE division
+// sequence cost 0.4 ms of a 5 ms FP64 step), capped at 1; the denominator is
+// guarded so that d1 = d2 = 0 gives 0.  Float on the device: the weight from
+// the hardware reciprocal, saturated to [0, 1] by the VALU clamp, which also
+// sends the 0 * inf of d1 = d2 = 0 to 0.  The host emulation divides.
 template <class R>
 PCLB_HD inline R mwb_lim(R d1, R d2);
 template <>
 PCLB_HD inline double mwb_lim<double>(double d1, double d2) {
   const double a1 = fabs(d1), a2 = fabs(d2);
-  return (d1 - d2) * a1 / fmax(a1 + a2, 2.2250738585072014e-308);
+  const double s = fmax(a1 + a2, 2.2250738585072014e-308);
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(s);
+  r = fma(fma(-s, r, 1.0), r, r);
+  r = fma(fma(-s, r, 1.0), r, r);
+  return (d1 - d2) * fmin(a1 * r, 1.0);
+#else
+  // host emulation of the device arithmetic (tests only)
+  return (d1 - d2) * a1 / s;
+#endif
 }
 template <>
 PCLB_HD inline float mwb_lim<float>(float d1, float d2) {

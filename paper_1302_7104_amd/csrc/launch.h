@@ -25,6 +25,10 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
                              const StripTune& tune, hipStream_t s);
 template <class R>
 bool strip_supported(const Tables& T);
+// The FP64 strip kernel (full annulus, MWB, n_theta a multiple of 64).
+bool strip64_supported(const Tables& T);
+hipError_t launch_step_strip64(const Tables& T, const void* f, void* out, const void* ghost,
+                               const StripTune& tune, hipStream_t s);
 template <class R>
 hipError_t launch_init(const Tables& T, const double* rho, const double* ur, const double* ut,
                        const double* Tt, void* f, int* bad, hipStream_t s);

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "../../include/pclb.h"
 #include "common.h"
@@ -124,9 +125,13 @@ hipError_t do_step(pclb_ctx* c, const void* in, void* out, void* ghost) {
   hipError_t e = launch_ghost<R>(c->T, c->bc, in, ghost, c->stream);
   if (e != hipSuccess) return e;
   int kern = c->cfg.kernel;
-  if (kern == PCLB_KERNEL_STRIP || kern == PCLB_KERNEL_AUTO)
-    if (strip_supported<R>(c->T))
-      return launch_step_strip<R>(c->T, in, out, ghost, c->tune, c->stream);
+  if (kern == PCLB_KERNEL_STRIP || kern == PCLB_KERNEL_AUTO) {
+    if constexpr (std::is_same<R, float>::value) {
+      if (strip_supported<R>(c->T)) return launch_step_strip<R>(c->T, in, out, ghost, c->tune, c->stream);
+    } else {
+      if (strip64_supported(c->T)) return launch_step_strip64(c->T, in, out, ghost, c->tune, c->stream);
+    }
+  }
   return launch_step_node<R>(c->T, in, out, ghost, c->stream);
 }
 
