@@ -75,11 +75,12 @@ enum {
  * annulus (n_f = 8) with the MWB scheme and n_theta >= 64 whose planes it can
  * address with 32-bit offsets; its strips of 64 columns that straddle an
  * octant boundary theta = m pi/4 (none when n_theta is a multiple of 512) run
- * in a second launch of a variant that selects upwind sides per lane.
- * Everything else (double states, sectors, the comparison schemes, narrow
- * grids) runs on the node kernel, whatever is asked.  The double and triple
- * octagon run on a kernel of their own (one thread per node, velocities in a
- * loop) whatever is asked. */
+ * in a second launch of a variant that selects upwind sides per lane.  Its
+ * double form runs double states of the full annulus with the MWB scheme and
+ * n_theta a multiple of 64.  Everything else (sectors, the comparison
+ * schemes, other grids) runs on the node kernel, whatever is asked.  The
+ * double and triple octagon run on a kernel of their own (one thread per
+ * node, velocities in a loop) whatever is asked. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
