@@ -81,6 +81,20 @@ __host__ __device__ inline double weight_k_prime(double E) {
   return WC<K, 0>::v + E * (2.0 * WC<K, 1>::v + E * (3.0 * WC<K, 2>::v + E * 4.0 * WC<K, 3>::v));
 }
 
+// 1/x in double.  On the device: the hardware reciprocal refined by two
+// Newton steps (within an ulp or two of the IEEE quotient, at a fraction of
+// the division sequence's cost; every FP64 division of the step is one of
+// these).  The host emulation divides.
+PCLB_HD inline double recip_d(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 // Everything a step launch needs besides the state buffers.
 struct Tables {
   int32_t nr, nth;
@@ -133,7 +147,7 @@ struct EqCoef {
 
 PCLB_HD inline void eq_setup(const Tables&, double rho, double ux, double uy, double E,
                              EqCoef& c) {
-  double iE = 1.0 / E;
+  double iE = recip_d(E);
   const double F1 = weight_k<0>(E), F2 = weight_k<1>(E), F3 = weight_k<2>(E), F4 = weight_k<3>(E);
   c.rF[1] = rho * F1;
   c.rF[2] = rho * F2;
@@ -196,7 +210,7 @@ PCLB_HD inline void combine_partials(const double P[4][4], double f0, double& rh
   const double jy = ((P[0][2] + P[1][2]) + P[2][2]) + P[3][2];
   const double eps = ((P[0][3] + P[1][3]) + P[2][3]) + P[3][3];
   rho = r;
-  const double ir = 1.0 / r;
+  const double ir = recip_d(r);
   ux = jx * ir;
   uy = jy * ir;
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
@@ -323,10 +337,9 @@ PCLB_HD inline void courant(R vk, R a, R& aC, R& K) {
 // and whose limiter part is 0 when d1 = d2 = 0.
 //
 // Limiter part (d1 - d2) |d1| / (|d1| + |d2|).  Double on the device: the
-// weight |d1| / (|d1| + |d2|) from the hardware reciprocal refined by two
-// Newton steps (within an ulp or two of the quotient; the IEEE division
-// sequence cost 0.4 ms of a 5 ms FP64 step), capped at 1; the denominator is
-// guarded so that d1 = d2 = 0 gives 0.  Float on the device: the weight from
+// weight |d1| / (|d1| + |d2|) with recip_d (the IEEE division sequence cost
+// 0.4 ms of a 5 ms FP64 step), capped at 1; the denominator is guarded so
+// that d1 = d2 = 0 gives 0.  Float on the device: the weight from
 // the hardware reciprocal, saturated to [0, 1] by the VALU clamp, which also
 // sends the 0 * inf of d1 = d2 = 0 to 0.  The host emulation divides.
 template <class R>
@@ -336,10 +349,7 @@ PCLB_HD inline double mwb_lim<double>(double d1, double d2) {
   const double a1 = fabs(d1), a2 = fabs(d2);
   const double s = fmax(a1 + a2, 2.2250738585072014e-308);
 #if defined(__HIP_DEVICE_COMPILE__)
-  double r = __builtin_amdgcn_rcp(s);
-  r = fma(fma(-s, r, 1.0), r, r);
-  r = fma(fma(-s, r, 1.0), r, r);
-  return (d1 - d2) * fmin(a1 * r, 1.0);
+  return (d1 - d2) * fmin(a1 * recip_d(s), 1.0);
 #else
   // host emulation of the device arithmetic (tests only)
   return (d1 - d2) * a1 / s;

@@ -135,7 +135,7 @@ __device__ inline void eq_models(double rho, double ux, double uy, double E, EqC
   c.rF[3] = rho * F3;
   c.rF[4] = rho * F4;
   c.rF[0] = rho * (1.0 - row_b<NI>().b0 * (((F1 + F2) + F3) + F4));
-  const double iE = 1.0 / E, u2 = ux * ux + uy * uy, a = 0.5 * u2 * iE, g = 1.0 - a;
+  const double iE = recip_d(E), u2 = ux * ux + uy * uy, a = 0.5 * u2 * iE, g = 1.0 - a;
   const double iE2 = iE * iE;
   c.A0 = g + 0.5 * a * a;
   c.A1 = g * iE;
@@ -196,7 +196,7 @@ __device__ inline void moments_of(Get get, double& rho, double& ux, double& uy, 
   const double f0 = get(0);
   if (fin) *fin = ok && isfinite(f0);
   rho = r + f0;
-  const double ir = 1.0 / rho;
+  const double ir = recip_d(rho);
   ux = jx * ir;
   uy = jy * ir;
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);

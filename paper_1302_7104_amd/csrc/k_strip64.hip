@@ -19,7 +19,8 @@
 // from the adjacent lanes (ds_bpermute of the centre row); the two columns
 // beyond each end of the strip come from a halo read one row ahead with one
 // 16-byte load per lane (lane v: the pair left of the strip for velocity v,
-// lane 8 + v: the pair right of it).
+// lane 8 + v: the pair right of it), which the edge lanes fetch with
+// ds_bpermute as well.
 #include <type_traits>
 
 #include "common.h"
@@ -76,13 +77,6 @@ __device__ inline double pick(uint64_t m, double a, double b) {
   return __builtin_bit_cast(double, (__builtin_bit_cast(uint64_t, a) & m) | (__builtin_bit_cast(uint64_t, b) & ~m));
 }
 
-__device__ inline double rl(double x, int lane) {
-  const int64_t b = __builtin_bit_cast(int64_t, x);
-  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __builtin_bit_cast(double, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-}
-
 template <int W>
 __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i0, int i1,
                                  double* lds) {
@@ -92,17 +86,25 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
   DirGeom<double> G;
   dir_geometry(T.cth[X.j], T.sth[X.j], octant_of(X.j, X.nth, ND), T.dt_dr, T.dt_dth, G);
   const double e = T.e, ome = 1.0 - T.e;
-  bool tb[2];
-  uint64_t rm[2];     // all ones where the member is radially upwind-backward
-  int a1[2], a2[2];   // ds_bpermute byte addresses of the lanes one and two upwind in theta
+  // per member h of the pair: radial upwind side (all ones where backward),
+  // the lanes one and two upwind in theta, the halo lane base of the upwind
+  // side (0: left pairs, 8: right pairs), and whether this lane's u1 lies
+  // beyond the strip (e1) or its u2 is the first column beyond it (e2)
+  uint64_t rm[2];
+  int a1[2], a2[2], eb[2];
+  bool e1[2], e2[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     rm[h] = ((G.rback >> (d4 + 4 * h)) & 1u) ? ~0ull : 0ull;
-    tb[h] = (G.tback >> (d4 + 4 * h)) & 1u;
-    const int sc = tb[h] ? -1 : 1;
-    a1[h] = ((lane + sc) & 63) << 2;
-    a2[h] = ((lane + 2 * sc) & 63) << 2;
+    const bool tb = (G.tback >> (d4 + 4 * h)) & 1u;
+    const int sc = tb ? -1 : 1;
+    a1[h] = (lane + sc) & 63;
+    a2[h] = (lane + 2 * sc) & 63;
+    eb[h] = tb ? 0 : 8;
+    e1[h] = tb ? lane == 0 : lane == 63;
+    e2[h] = tb ? lane == 1 : lane == 62;
   }
+  const bool left_lane = (lane & 15) < 8;   // lanes holding a left halo pair
   // the ring: S[s][v] holds row (i - 2 + s) at slot (u + s) mod 6 of row i = ib + u
   double S[S64_RING][S64_NV];
   const int last = i1 + 1;   // the furthest row any update of the chunk reads
@@ -158,6 +160,9 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
       const size_t c0 = (size_t)i * X.nth + X.j;
       if constexpr (W == 0)
         __builtin_nontemporal_store(relax_rest<double>(relax_rest_share(ec, ome), e, rcur), X.out + c0);
+      // halo by role: H1 the column next to the strip (j0 - 1 / j0 + 64), H2
+      // the one beyond it (j0 - 2 / j0 + 65)
+      const double H1 = left_lane ? hcur.y : hcur.x, H2 = left_lane ? hcur.x : hcur.y;
       const double rinv = T.rinv[i];
       const double atr = G.at[d4] * rinv;
 #pragma unroll
@@ -180,18 +185,12 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
           const double c = slot(2, v);
           const double u1r = pick(rm[h], slot(1, v), slot(3, v));
           const double u2r = pick(rm[h], slot(0, v), slot(4, v));
-          // azimuthal neighbours: adjacent lanes, the strip's edge lanes from the halo
-          const double hl2 = rl(hcur.x, v), hl1 = rl(hcur.y, v);
-          const double hr1 = rl(hcur.x, 8 + v), hr2 = rl(hcur.y, 8 + v);
-          const double z1 = __shfl(c, a1[h] >> 2), z2 = __shfl(c, a2[h] >> 2);
-          double u1t, u2t;
-          if (tb[h]) {
-            u1t = lane == 0 ? hl1 : z1;
-            u2t = lane == 0 ? hl2 : (lane == 1 ? hl1 : z2);
-          } else {
-            u1t = lane == 63 ? hr1 : z1;
-            u2t = lane == 63 ? hr2 : (lane == 62 ? hr1 : z2);
-          }
+          // azimuthal neighbours: adjacent lanes; the strip's edge lanes take
+          // velocity v's halo of their upwind side
+          const double z1 = __shfl(c, a1[h]), z2 = __shfl(c, a2[h]);
+          const double g1 = __shfl(H1, eb[h] + v), g2 = __shfl(H2, eb[h] + v);
+          const double u1t = e1[h] ? g1 : z1;
+          const double u2t = e1[h] ? g2 : (e2[h] ? g1 : z2);
           const double res = mwb_update<double>(rel[h], c, aCr, Kr, u1r, u2r, aCt, Kt, u1t, u2t);
           __builtin_nontemporal_store(res, X.out + s64_q<W>(v) * X.plane + c0);
         }
