@@ -14,6 +14,7 @@
 #include "common.h"
 #include "diag.h"
 #include "launch.h"
+#include "strip_common.h"
 
 namespace pclb {
 
@@ -174,32 +175,68 @@ __device__ inline void for_each_pair(Fn&& fn) {
   }
 }
 
-// rho, u, E of one node (Eqs. moment1-moment3) from its values get(q), summed
-// per opposite pair (sp = f_d + f_{d+N/2}, sm = f_d - f_{d+N/2}) with the
-// rest velocity last; jeps, if given, receives rho u_x, rho u_y and the
-// energy density sum f v^2 / 2.  fin becomes false if a value is not finite.
-template <int NI, class Get>
-__device__ inline void moments_of(Get get, double& rho, double& ux, double& uy, double& E,
-                                  double* jeps = nullptr, bool* fin = nullptr) {
+// Moment partials of the opposite pair (d, d + N_i/2) over the four speeds,
+// from the pair's values fp[k-1] (direction d) and fm[k-1] (d + N_i/2): with
+// sp = fp + fm and sm = fp - fm, P = (sum sp, sum v_k c_d sm, sum v_k s_d sm,
+// sum v_k^2 sp), speeds in order.
+template <int NI>
+__device__ inline void pair_partial(int d, const double* fp, const double* fm, double* P) {
+  const double cd = dirs<NI>().c[d], sd = dirs<NI>().s[d];
   double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
-  bool ok = true;
-  for_each_pair<NI>([&](auto kc, int d, int qp, int qm) {
-    constexpr int k = decltype(kc)::value;
-    const double a = get(qp), b = get(qm);
-    if (fin) ok = ok && isfinite(a) && isfinite(b);
-    const double sp = a + b, sm = a - b;
+#pragma unroll
+  for (int k = 1; k <= NK; ++k) {
+    const double sp = fp[k - 1] + fm[k - 1], sm = fp[k - 1] - fm[k - 1];
     r += sp;
-    jx += (speed(k) * dirs<NI>().c[d]) * sm;
-    jy += (speed(k) * dirs<NI>().s[d]) * sm;
+    jx += (speed(k) * cd) * sm;
+    jy += (speed(k) * sd) * sm;
     eps += (speed(k) * speed(k)) * sp;
-  });
-  const double f0 = get(0);
-  if (fin) *fin = ok && isfinite(f0);
+  }
+  P[0] = r;
+  P[1] = jx;
+  P[2] = jy;
+  P[3] = eps;
+}
+
+// rho, u, E from the sums of the pair partials (taken in pair order) and the
+// rest velocity's value, added last (Eqs. moment1-moment3).
+__device__ inline void moments_from_sums(double r, double jx, double jy, double eps, double f0,
+                                         double& rho, double& ux, double& uy, double& E) {
   rho = r + f0;
   const double ir = recip_d(rho);
   ux = jx * ir;
   uy = jy * ir;
   E = 0.5 * eps * ir - 0.5 * (ux * ux + uy * uy);
+}
+
+// rho, u, E of one node from its values get(q): pair partials in the order
+// d = 0 .. N_i/2 - 1, then the rest velocity (every kernel of these models
+// sums in exactly this order); jeps, if given, receives rho u_x, rho u_y and
+// the energy density sum f v^2 / 2; fin becomes false if a value is not
+// finite.
+template <int NI, class Get>
+__device__ inline void moments_of(Get get, double& rho, double& ux, double& uy, double& E,
+                                  double* jeps = nullptr, bool* fin = nullptr) {
+  double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
+  bool ok = true;
+#pragma unroll 1
+  for (int d = 0; d < NI / 2; ++d) {
+    double fp[NK], fm[NK], P[4];
+#pragma unroll
+    for (int k = 1; k <= NK; ++k) {
+      const int qp = 1 + NI * (k - 1) + d;
+      fp[k - 1] = get(qp);
+      fm[k - 1] = get(qp + NI / 2);
+      if (fin) ok = ok && isfinite(fp[k - 1]) && isfinite(fm[k - 1]);
+    }
+    pair_partial<NI>(d, fp, fm, P);
+    r += P[0];
+    jx += P[1];
+    jy += P[2];
+    eps += P[3];
+  }
+  const double f0 = get(0);
+  if (fin) *fin = ok && isfinite(f0);
+  moments_from_sums(r, jx, jy, eps, f0, rho, ux, uy, E);
   if (jeps) {
     jeps[0] = jx;
     jeps[1] = jy;
@@ -431,6 +468,189 @@ __global__ void __launch_bounds__(DIAG_BLOCK) models_diag_kernel(Tables T, const
   diag_block_reduce(acc, rmin, tmin, bad, partial);
 }
 
+// ---------------------------------------------------------------------------
+// Strip form of the step (full annulus, MWB scheme, n_theta a multiple of
+// 64), the design of the octagon's FP64 strip kernel for N_i/2 direction
+// pairs: a workgroup of N_i/2 wavefronts owns a strip of 64 theta columns
+// (one per lane) and marches in r over a chunk of rows; wave W owns the pair
+// (W, W + N_i/2), eight velocities, and wave 0 also the rest velocity.  Each
+// owned velocity keeps six rows in registers (i-2 .. i+3 at row i; the load
+// of a row is issued two rows before its first use, the row loop unrolled
+// six times so the roles rotate at compile time).  Per row the waves
+// exchange their pair partials through LDS (one barrier, double-buffered by
+// row parity), each builds the node's equilibrium from their sum in pair
+// order, and updates its velocities with the node kernel's arithmetic, so the
+// two forms agree bit for bit.  Azimuthal neighbours come from the adjacent
+// lanes (ds_bpermute); the two columns beyond each end of the strip from a
+// halo read one row ahead (one load per lane: lane v the pair left of the
+// strip for velocity v, lane 8 + v the pair right of it).
+constexpr int MS_RING = 6;
+
+template <class R> struct Pair2;
+template <> struct Pair2<float> { using T = float2; };
+template <> struct Pair2<double> { using T = double2; };
+
+// a where m is all ones, b where it is zero (a select on the bits: a plain
+// select between two ring slots lets the compiler select their addresses
+// and keep the ring in scratch memory)
+__device__ inline float ms_pick(uint64_t m, float a, float b) {
+  return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a) & (uint32_t)m) |
+                                       (__builtin_bit_cast(uint32_t, b) & ~(uint32_t)m));
+}
+__device__ inline double ms_pick(uint64_t m, double a, double b) {
+  return __builtin_bit_cast(double, (__builtin_bit_cast(uint64_t, a) & m) | (__builtin_bit_cast(uint64_t, b) & ~m));
+}
+
+// d: this wave's direction pair (wave-uniform; one copy of the code serves
+// every wave, so that no wave holds another's values)
+template <class R, int NI>
+__device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __restrict__ out,
+                                const R* __restrict__ ghost, int d, int j0, int i0, int i1,
+                                double* lds) {
+  constexpr int NQM = nq_of<NI>(), NH = NI / 2, NV = 2 * NK;
+  const int nr = T.nr, nth = T.nth;
+  const size_t plane = (size_t)nr * nth;
+  const int lane = threadIdx.x & 63, j = j0 + lane;
+  auto qv = [&](int v) { return 1 + NI * (v >> 1) + d + NH * (v & 1); };   // v = 2 (k-1) + h
+  const double cd = dirs<NI>().c[d], sd = dirs<NI>().s[d];
+  const double ct = T.cth[j], st = T.sth[j];
+  const double vr = cd * ct + sd * st, vt = sd * ct - cd * st;   // per unit speed, direction d
+  const R ar = (R)(fabs(vr) * T.dt_dr), at0 = (R)(fabs(vt) * T.dt_dth);
+  const double e = T.e, ome = 1.0 - T.e;
+  // per member h (direction d, then d + N_i/2, whose components are negated)
+  uint64_t rm[2];
+  int a1[2], a2[2], eb[2];
+  bool e1[2], e2[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double svr = h ? -vr : vr, svt = h ? -vt : vt;
+    rm[h] = svr >= 0.0 ? ~0ull : 0ull;      // radially upwind-backward
+    const bool tb = svt >= 0.0;             // azimuthally upwind-backward
+    const int sc = tb ? -1 : 1;
+    a1[h] = (lane + sc) & 63;
+    a2[h] = (lane + 2 * sc) & 63;
+    eb[h] = tb ? 0 : 8;
+    e1[h] = tb ? lane == 0 : lane == 63;
+    e2[h] = tb ? lane == 1 : lane == 62;
+  }
+  const bool left_lane = (lane & 15) < 8;
+  auto load = [&](int v, int row) -> R {
+    if (row < 0) return ghost[gidx(0, -1 - row, qv(v), j, nth, NQM)];
+    if (row >= nr) return ghost[gidx(1, row - nr, qv(v), j, nth, NQM)];
+    return f[qv(v) * plane + (size_t)row * nth + j];
+  };
+  auto halo = [&](int row) -> typename Pair2<R>::T {
+    const int hl = lane & 15, v = hl & 7;
+    int c = hl < 8 ? j0 - 2 : j0 + 64;
+    c = c < 0 ? c + nth : (c >= nth ? c - nth : c);
+    return *reinterpret_cast<const typename Pair2<R>::T*>(f + qv(v) * plane + (size_t)row * nth + c);
+  };
+  R S[MS_RING][NV];
+  const int last = i1 + 1;   // the furthest row any update of the chunk reads
+#pragma unroll
+  for (int s = 0; s < MS_RING; ++s) {
+    const int row = i0 - 2 + s;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S[s][v] = row <= last ? load(v, row) : (R)0;
+  }
+  const bool rest = d == 0;   // wave 0 also owns the rest velocity
+  double r0 = 0.0;
+  if (rest) r0 = (double)f[(size_t)i0 * nth + j];
+  auto hv = halo(i0);
+  for (int ib = i0; ib < i1; ib += MS_RING) {
+#pragma unroll
+    for (int u = 0; u < MS_RING; ++u) {
+      const int i = ib + u;
+      if (i >= i1) break;
+      auto slot = [&](int sl, int v) -> R { return S[(u + sl) % MS_RING][v]; };
+      const auto hcur = hv;
+      if (i + 1 < i1) hv = halo(i + 1);
+      double rcur = r0;
+      if (rest && i + 1 < i1) r0 = (double)f[(size_t)(i + 1) * nth + j];
+      // pair partials, exchanged through LDS: buf[(p * 4 + a) * 64 + lane],
+      // the rest value at buf[NH * 4 * 64 + lane]
+      double* buf = lds + (i & 1) * ((NH * 4 + 1) * 64);
+      {
+        double fp[NK], fm[NK], P[4];
+#pragma unroll
+        for (int k = 1; k <= NK; ++k) {
+          fp[k - 1] = (double)slot(2, 2 * (k - 1));
+          fm[k - 1] = (double)slot(2, 2 * (k - 1) + 1);
+        }
+        pair_partial<NI>(d, fp, fm, P);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) buf[(d * 4 + a) * 64 + lane] = P[a];
+      }
+      if (rest) buf[NH * 4 * 64 + lane] = rcur;
+      __syncthreads();
+      rcur = buf[NH * 4 * 64 + lane];
+      double r = 0.0, jx = 0.0, jy = 0.0, eps = 0.0;
+      // (not unrolled: all N_i/2 partials in flight at once would take
+      // 4 N_i registers)
+#pragma unroll 1
+      for (int p = 0; p < NH; ++p) {
+        r += buf[(p * 4 + 0) * 64 + lane];
+        jx += buf[(p * 4 + 1) * 64 + lane];
+        jy += buf[(p * 4 + 2) * 64 + lane];
+        eps += buf[(p * 4 + 3) * 64 + lane];
+      }
+      double rho, ux, uy, E;
+      moments_from_sums(r, jx, jy, eps, rcur, rho, ux, uy, E);
+      EqCoef ec;
+      eq_models<NI>(rho, ux, uy, E, ec);
+      const size_t c0 = (size_t)i * nth + j;
+      if (rest) out[c0] = relax_rest<R>(relax_rest_share(ec, ome), e, rcur);
+      const typename Pair2<R>::T H1v = hcur, H2v = hcur;
+      const R H1 = left_lane ? H1v.y : H1v.x, H2 = left_lane ? H2v.x : H2v.y;
+      const R rinv = (R)T.rinv[i];
+      const R at = at0 * rinv;
+      const double pd = ux * cd + uy * sd;
+      for_k<1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int v0 = 2 * (k - 1);
+        double rel[2];
+        relax_pair<k>(ec, e, ome, pd, (double)slot(2, v0), (double)slot(2, v0 + 1), rel[0], rel[1]);
+        R aCr, Kr, aCt, Kt;
+        courant<R>((R)speed(k), ar, aCr, Kr);
+        courant<R>((R)speed(k), at, aCt, Kt);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int v = v0 + h;
+          const R c = slot(2, v);
+          const R u1r = ms_pick(rm[h], slot(1, v), slot(3, v));
+          const R u2r = ms_pick(rm[h], slot(0, v), slot(4, v));
+          const R z1 = __shfl(c, a1[h]), z2 = __shfl(c, a2[h]);
+          const R g1 = __shfl(H1, eb[h] + v), g2 = __shfl(H2, eb[h] + v);
+          const R u1t = e1[h] ? g1 : z1;
+          const R u2t = e1[h] ? g2 : (e2[h] ? g1 : z2);
+          const R tr = conv_term<SCH_MWB, R>(aCr, Kr, c, u1r, u2r, c);
+          const R tt = conv_term<SCH_MWB, R>(aCt, Kt, c, u1t, u2t, c);
+          out[qv(v) * plane + c0] = (R)((rel[h] - (double)tr) - (double)tt);
+        }
+      });
+      // look-ahead: row i + 4 into the slot of row i - 2
+      const int row = i + 4;
+      if (row <= last) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[u % MS_RING][v] = load(v, row);
+      }
+    }
+  }
+}
+
+template <class R, int NI>
+__global__ void __launch_bounds__(64 * (NI / 2))
+models_strip_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
+                    const R* __restrict__ ghost, int chunk) {
+  __shared__ double lds[2 * ((NI / 2) * 4 + 1) * 64];
+  const int nstrip = T.nth / 64;
+  const int item = strip::work_item(1);
+  const int strip_i = item % nstrip, ck = item / nstrip;
+  const int j0 = strip_i * 64;
+  const int i0 = ck * chunk, i1 = min(i0 + chunk, T.nr);
+  ms_march<R, NI>(T, f, out, ghost, __builtin_amdgcn_readfirstlane(threadIdx.x / 64), j0, i0, i1, lds);
+}
+
 }  // namespace
 
 template <class R>
@@ -462,9 +682,26 @@ void launch_models_step_ni(const Tables& T, dim3 grid, const R* f, R* out, const
   }
 }
 
+// The strip form serves the double octagon.  For the triple octagon its
+// twelve waves per workgroup must fit in 168 registers each, which spills
+// the ring (FP32 12.9 ms against 11.8 for the per-node form at 4096 x 8192,
+// FP64 34 ms against 18), so it keeps the per-node form.
+bool models_strip_supported(const Tables& T, int ni) {
+  return ni == 16 && T.nf == ni && T.scheme == SCH_MWB && T.nth >= 64 && T.nth % 64 == 0;
+}
+
 template <class R>
 hipError_t launch_models_step(const Tables& T, int ni, const void* f, void* out, const void* ghost,
-                              hipStream_t s) {
+                              const StripTune& tune, bool strip, hipStream_t s) {
+  if (strip && models_strip_supported(T, ni)) {   // ni == 16
+    int chunk = tune.chunk > 0 ? tune.chunk : 32;
+    const int strips = T.nth / 64;
+    while (tune.chunk <= 0 && chunk > 8 && (long)strips * ((T.nr + chunk - 1) / chunk) < 4096) chunk /= 2;
+    const dim3 grid(strips * ((T.nr + chunk - 1) / chunk));
+    hipLaunchKernelGGL((models_strip_kernel<R, 16>), grid, dim3(64 * 8), 0, s, T, (const R*)f, (R*)out,
+                       (const R*)ghost, chunk);
+    return hipGetLastError();
+  }
   const dim3 grid((T.nth + 255) / 256, T.nr);
   if (ni == 16) launch_models_step_ni<R, 16>(T, grid, (const R*)f, (R*)out, (const R*)ghost, s);
   else launch_models_step_ni<R, 24>(T, grid, (const R*)f, (R*)out, (const R*)ghost, s);
@@ -510,7 +747,7 @@ hipError_t launch_models_diag(const Tables& T, int ni, const void* f, double* pa
   template hipError_t launch_models_ghost<R>(const Tables&, int, const BCdev&, const void*, void*, \
                                              hipStream_t);                                         \
   template hipError_t launch_models_step<R>(const Tables&, int, const void*, void*, const void*,   \
-                                            hipStream_t);                                          \
+                                            const StripTune&, bool, hipStream_t);                  \
   template hipError_t launch_models_init<R>(const Tables&, int, const double*, const double*,      \
                                             const double*, const double*, void*, int*, hipStream_t); \
   template hipError_t launch_models_fields<R>(const Tables&, int, const void*, double*, double*,   \

@@ -51,9 +51,10 @@ hipError_t launch_diag_final(const double* partial, int nb, double step, double*
 template <class R>
 hipError_t launch_models_ghost(const Tables& T, int ni, const BCdev& bc, const void* f, void* ghost,
                                hipStream_t s);
+// strip: the strip form may be used (full annulus, MWB, n_theta a multiple of 64)
 template <class R>
 hipError_t launch_models_step(const Tables& T, int ni, const void* f, void* out, const void* ghost,
-                              hipStream_t s);
+                              const StripTune& tune, bool strip, hipStream_t s);
 template <class R>
 hipError_t launch_models_init(const Tables& T, int ni, const double* rho, const double* ur,
                               const double* ut, const double* Tt, void* f, int* bad, hipStream_t s);

@@ -120,7 +120,8 @@ hipError_t do_step(pclb_ctx* c, const void* in, void* out, void* ghost) {
   if (c->cfg.n_i != 8) {
     hipError_t e = launch_models_ghost<R>(c->T, c->cfg.n_i, c->bc, in, ghost, c->stream);
     if (e != hipSuccess) return e;
-    return launch_models_step<R>(c->T, c->cfg.n_i, in, out, ghost, c->stream);
+    const bool strip = c->cfg.kernel == PCLB_KERNEL_STRIP || c->cfg.kernel == PCLB_KERNEL_AUTO;
+    return launch_models_step<R>(c->T, c->cfg.n_i, in, out, ghost, c->tune, strip, c->stream);
   }
   hipError_t e = launch_ghost<R>(c->T, c->bc, in, ghost, c->stream);
   if (e != hipSuccess) return e;

@@ -170,3 +170,46 @@ def test_octagon_only_entry_points_refuse_larger_models():
     out = torch.empty_like(s.state)
     with pytest.raises(PclbError, match="octagon"):
         s.adjoint_step(s.state, lam, out)
+
+
+@pytest.mark.parametrize("ni", [16])
+@pytest.mark.parametrize("shape", [(9, 128), (21, 192), (6, 64)])
+def test_strip_form_bitwise_equals_node_form(ni, shape):
+    """The strip form of the double octagon (full annulus, MWB, n_theta a
+    multiple of 64) gives the per-node form's result bit for bit, in both
+    precisions, for chunks of 1, 5 and 64 rows and the default: chunk tails,
+    chunks next to both walls, single-strip grids and strips whose edge halo
+    wraps around the ring.  (The triple octagon keeps the per-node form.)"""
+    from paper_1302_7104_amd import _native as N
+    from paper_1302_7104_amd.sim import Sim
+    nr, nth = shape
+    P, F = problem(ni, ni, nr, nth, BCS[2], 10)
+    for prec in (32, 64):
+        ref = Sim(P, precision=prec, kernel=N.KERNEL_NODE)
+        ref.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        ref.step(6)
+        want = ref.state.cpu().numpy()
+        ref.close()
+        for chunk in (0, 1, 5, 64):
+            s = Sim(P, precision=prec, kernel=N.KERNEL_STRIP, strip_chunk=chunk)
+            s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+            s.step(6)
+            got = s.state.cpu().numpy()
+            s.close()
+            assert np.array_equal(got, want), (ni, shape, prec, chunk)
+
+
+@pytest.mark.parametrize("ni", [16, 24])
+def test_strip_form_parity(ni):
+    """The default kernel choice on a grid the strip form takes (n_theta =
+    256: four strips) against the oracle: the strip form for the double
+    octagon, the per-node form for the triple."""
+    P, F = problem(ni, ni, 10, 256, BCS[1], 11)
+    for prec, tol in ((64, FP64_TOL), (32, FP32_TOL)):
+        s, f0 = start(P, F, prec, 12)
+        s.step(5)
+        got = s.state.double().cpu().numpy()
+        want, bad = O.step(grid_of(P), f0, 5)
+        assert bad == 0
+        assert rel(got, want) <= tol, (ni, prec, rel(got, want))
+        s.close()
