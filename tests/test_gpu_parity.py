@@ -41,6 +41,16 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def node_err(a, b):
+    """Largest error of one node's values relative to the size of that node's
+    distribution (sum over q of |f_q|): an error confined to a few nodes,
+    which a norm over the whole grid can hide, shows here."""
+    return float((np.abs(a - b).max(0) / np.abs(b).sum(0)).max())
+
+
+NODE_TOL = {64: 1e-13, 32: 1e-6}
+
+
 def start(P, F, precision, noise_seed=None, amp=1e-3, kernel=0):
     """Same initial state on both sides: f^eq(fields) times (1 + noise)."""
     s = sim_of(P, precision, kernel)
@@ -74,6 +84,7 @@ def test_init_state_matches_oracle():
         got = s.state.double().cpu().numpy()
         want = O.init_feq(grid_of(P), **F)
         assert rel(got, want) <= tol, (prec, rel(got, want))
+        assert node_err(got, want) <= NODE_TOL[prec], node_err(got, want)
 
 
 @pytest.mark.parametrize("bc", BCS)
@@ -86,6 +97,7 @@ def test_step_parity_fp64_small(bc, kernel):
     want, bad = O.step(grid_of(P), f0, 5)
     assert bad == 0
     assert rel(got, want) <= FP64_TOL, rel(got, want)
+    assert node_err(got, want) <= NODE_TOL[64], node_err(got, want)
 
 
 BCS_NEQ = [((W.WALL | W.NONEQ, (0.2, 0, 0, 0)), (W.INFLOW | W.NONEQ, (0.9, -0.03, 0.1, 0.95))),
@@ -106,6 +118,7 @@ def test_step_parity_noneq_boundary(bc, kernel):
         want, bad = O.step(grid_of(P), f0, 5)
         assert bad == 0
         assert rel(got, want) <= tol, (prec, rel(got, want))
+        assert node_err(got, want) <= NODE_TOL[prec], node_err(got, want)
         s.close()
 
 
@@ -117,6 +130,7 @@ def test_step_parity_fp32_small(bc):
     got = s.state.double().cpu().numpy()
     want, _ = O.step(grid_of(P), f0, 5)
     assert rel(got, want) <= 2e-7, rel(got, want)
+    assert node_err(got, want) <= NODE_TOL[32], node_err(got, want)
 
 
 def test_rotation_config_fp64_full():
@@ -542,6 +556,44 @@ def test_fd_matches_fp64_adjoint_gradient():
                    for k in range(13)])
     err = np.abs(g - fd).max() / np.abs(fd).max()
     print(f"FD (h = 1e-6) vs FP64 adjoint, 20 steps at 1024x2048: {err:.2e}")
+    assert err <= 1e-4, err
+
+
+@pytest.mark.xfail(strict=False, reason="over 200 steps the MWB switch changes branch at nodes whose "
+                   "upwind differences cross zero for perturbations far below h = 1e-4, so central "
+                   "differences do not converge to the derivative of the discrete map (measured "
+                   "disagreement 1e-1 to 3e-1 at h = 1e-4, 1e-2 at h = 1e-6; 20 steps agree to 3e-5)")
+def test_fd_matches_adjoint_gradient_at_the_configured_run():
+    """The adjoint run as configured: Richtmyer-Meshkov on 1024 x 2048, 200
+    steps, checkpoints every 20, FP64, central differences with h = 1e-4,
+    target agreement 1e-4 (not reached; the measured figure is printed)."""
+    from paper_1302_7104_amd.sim import Evolve, InitState
+    nr, nth, steps = 1024, 2048, 200
+    a0 = W.rm_amplitudes(1)
+    P, _ = W.richtmyer_meshkov(nr, nth, steps)
+    band_np = band_weight(P)
+    s = sim_of(P, 64)
+    amps = torch.as_tensor(a0, device=s.device).requires_grad_(True)
+    _, Ft = W.richtmyer_meshkov(nr, nth, steps, amps=amps, xp=torch)
+    f0 = InitState.apply(s, Ft["rho"], Ft["ur"], Ft["ut"], Ft["T"])
+    fn = Evolve.apply(s, f0, steps, 20)
+    band = torch.as_tensor(band_np, device=s.device)
+    J = ((fn.sum(0) ** 2) * band).sum()
+    J.backward()
+    g = amps.grad.detach().cpu().numpy()
+
+    def J_of(a):
+        _, F = W.richtmyer_meshkov(nr, nth, steps, amps=a)
+        s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        s.step(steps)
+        return float(((s.state.sum(0) ** 2) * band).sum().item())
+
+    h = 1e-4
+    fd = np.array([(J_of(a0 + h * np.eye(13)[k]) - J_of(a0 - h * np.eye(13)[k])) / (2 * h)
+                   for k in range(13)])
+    err = np.abs(g - fd).max() / np.abs(fd).max()
+    print(f"FD (h = 1e-4) vs FP64 adjoint, 200 steps at 1024x2048: {err:.2e}")
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
     assert err <= 1e-4, err
 
 
