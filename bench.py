@@ -161,6 +161,32 @@ def run_models(W, Sim, torch, steps=20, warmup=3):
     return out
 
 
+def graph_replay_rotation(W, Sim, torch, steps=200, reps=5):
+    """The rotation configuration (64 x 128, 200 steps): per-step time of
+    eager launches (pclb_step) against one replayed HIP graph of the 200
+    steps (pclb_step_graph), FP32; the grid is small enough for launches to
+    dominate."""
+    P, F = W.rotation(64, 128, steps)
+    out = {}
+    for name in ("eager", "graph"):
+        sim = Sim(P, precision=32)
+        sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        run = sim.step if name == "eager" else sim.step_graph
+        run(steps)                          # warm-up (and the capture)
+        st = sim.stream
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(reps):
+            run(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        out[f"{name}_us_per_step"] = e0.elapsed_time(e1) * 1e3 / (reps * steps)
+        sim.close()
+    return out
+
+
 def couette_errors(W, Sim, torch):
     """Sec. III.A: the one-eighth-sector rotating-cylinder run (100 x 20) from
     rest to steady state in FP64 for each relaxation time; the largest
@@ -559,7 +585,9 @@ def main():
             print(json.dumps({name: fp32_accuracy(W, torch, name)}), flush=True)
         return
     if args.models_only:
-        print(json.dumps({"double_triple_octagon_kh4096x8192": run_models(W, Sim, torch)}), flush=True)
+        print(json.dumps({"double_triple_octagon_kh4096x8192": run_models(W, Sim, torch),
+                          "rotation_64x128_graph_replay": graph_replay_rotation(W, Sim, torch)}),
+              flush=True)
         return
     if args.variants_only:
         print(json.dumps({"schemes_and_noneq_kh4096x8192_fp32": run_variants(W, Sim, torch)}),
@@ -606,6 +634,7 @@ def main():
                                                  for name in ACCURACY_RUNS}
         extra["schemes_and_noneq_kh4096x8192_fp32"] = run_variants(W, Sim, torch)
         extra["double_triple_octagon_kh4096x8192"] = run_models(W, Sim, torch)
+        extra["rotation_64x128_graph_replay"] = graph_replay_rotation(W, Sim, torch)
         extra["couette_sector_steady_error"] = couette_errors(W, Sim, torch)
         extra["rm_sector_compression"] = rm_sector_runs(W, Sim)
     out["extra"] = extra

@@ -82,7 +82,9 @@ enum {
  * double and triple octagon run on a kernel of their own (one thread per
  * node, velocities in a loop) whatever is asked. */
 enum {
-  PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it */
+  PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it and gives it at least
+                              512 workgroups (64-column strips times chunks of 8 rows), else
+                              the node kernel */
   PCLB_KERNEL_NODE = 1,    /* one thread per node, neighbours read from global memory */
   PCLB_KERNEL_STRIP = 2    /* r-marching 64-column theta strips with a register ring */
 };
@@ -207,6 +209,16 @@ int pclb_step(pclb_ctx* ctx, int64_t n);
  * uses that GPU's one array: calls that overlap in time on one GPU (other
  * streams, other threads) race and must not be issued. */
 int pclb_step_static(pclb_ctx* ctx, int64_t n);
+
+/* pclb_step as one HIP graph launch (for small grids, whose steps are
+ * dominated by launch overhead): the first call captures the n steps'
+ * kernel launches from the current buffer into a graph on a stream of the
+ * context and instantiates it; later calls with the same n, the same current
+ * buffer and no pclb_set_bc or pclb_bind in between replay it; anything else
+ * captures again.  The same steps as pclb_step, bit for bit.  PCLB_EINVAL for
+ * n outside 0..100000; PCLB_EDEVICE if capture, instantiation or launch
+ * fails.  Asynchronous on the bound stream. */
+int pclb_step_graph(pclb_ctx* ctx, int64_t n);
 
 /* One step from an arbitrary caller buffer f_in to f_out (both device
  * buffers of the context's element type and size; they must not overlap).

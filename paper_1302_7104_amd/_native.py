@@ -30,6 +30,7 @@ SYMBOLS = (
     "pclb_set_bc", "pclb_init_state", "pclb_step", "pclb_step_into", "pclb_current",
     "pclb_step_count", "pclb_moments", "pclb_moments_of", "pclb_moments_host",
     "pclb_adjoint_step", "pclb_adjoint_init", "pclb_step_static", "pclb_noneq",
+    "pclb_step_graph",
 )
 
 
@@ -80,6 +81,7 @@ def lib():
     L.pclb_init_state.argtypes = [P, _V, _V, _V, _V]
     L.pclb_step.argtypes = [P, ctypes.c_int64]
     L.pclb_step_static.argtypes = [P, ctypes.c_int64]
+    L.pclb_step_graph.argtypes = [P, ctypes.c_int64]
     L.pclb_step_into.argtypes = [P, _V, _V]
     L.pclb_current.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     L.pclb_step_count.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]

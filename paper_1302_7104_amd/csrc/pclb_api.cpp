@@ -45,6 +45,15 @@ struct pclb_ctx {
   int* d_flag = nullptr;        // init validation flag
   double* d_gm = nullptr;       // adjoint: ghost moment cotangents 2*2*4*nth
   void* d_scratch = nullptr;    // this device's copy of the static scratch array
+  // pclb_step_graph: the executable graph of `gsteps` steps starting from
+  // buffer `gcur`, captured on `gstream` (a non-blocking stream of the
+  // context) at configuration stamp `gstamp`; `stamp` moves with every
+  // pclb_set_bc and pclb_bind, which change what the kernels are given
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t gsteps = 0;
+  int gcur = -1;
+  uint64_t gstamp = 0, stamp = 1;
   std::string err;
 };
 
@@ -115,18 +124,31 @@ int validate(const pclb_config* c, std::string& why) {
   return PCLB_OK;
 }
 
+// The strip kernels march one workgroup per (64-column strip, chunk of at
+// least 8 rows); with fewer than 512 such workgroups a grid leaves most of
+// the GPU idle and the one-thread-per-node kernel is faster (measured: 25
+// against 50 us per FP32 step at 64 x 128, 31 against 43 at 256 x 512; the
+// strip kernel wins from 512 x 1024 on, 55 against 78 us).  Only the
+// automatic choice looks at this; an explicit PCLB_KERNEL_STRIP is obeyed
+// wherever the strip kernel can run.
+bool strip_pays(const pclb_ctx* c) {
+  const pclb_config& g = c->cfg;
+  return g.kernel == PCLB_KERNEL_STRIP ||
+         (int64_t)((g.n_theta + 63) / 64) * ((g.n_r + 7) / 8) >= 512;
+}
+
 template <class R>
 hipError_t do_step(pclb_ctx* c, const void* in, void* out, void* ghost) {
   if (c->cfg.n_i != 8) {
     hipError_t e = launch_models_ghost<R>(c->T, c->cfg.n_i, c->bc, in, ghost, c->stream);
     if (e != hipSuccess) return e;
-    const bool strip = c->cfg.kernel == PCLB_KERNEL_STRIP || c->cfg.kernel == PCLB_KERNEL_AUTO;
+    const bool strip = (c->cfg.kernel == PCLB_KERNEL_STRIP || c->cfg.kernel == PCLB_KERNEL_AUTO) && strip_pays(c);
     return launch_models_step<R>(c->T, c->cfg.n_i, in, out, ghost, c->tune, strip, c->stream);
   }
   hipError_t e = launch_ghost<R>(c->T, c->bc, in, ghost, c->stream);
   if (e != hipSuccess) return e;
   int kern = c->cfg.kernel;
-  if (kern == PCLB_KERNEL_STRIP || kern == PCLB_KERNEL_AUTO) {
+  if ((kern == PCLB_KERNEL_STRIP || kern == PCLB_KERNEL_AUTO) && strip_pays(c)) {
     if constexpr (std::is_same<R, float>::value) {
       if (strip_supported<R>(c->T)) return launch_step_strip<R>(c->T, in, out, ghost, c->tune, c->stream);
     } else {
@@ -244,6 +266,8 @@ int pclb_create(const pclb_config* cfg, pclb_ctx** out) {
 
 void pclb_destroy(pclb_ctx* c) {
   if (!c) return;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->d_geom) (void)hipFree(c->d_geom);
   if (c->d_ghost) (void)hipFree(c->d_ghost);
   if (c->d_partial) (void)hipFree(c->d_partial);
@@ -266,6 +290,7 @@ int pclb_bind(pclb_ctx* c, void* f0, void* f1, void* stream) {
   c->stream = (hipStream_t)stream;
   c->bound = true;
   c->steps = 0;
+  ++c->stamp;
   return PCLB_OK;
 }
 
@@ -287,6 +312,7 @@ int pclb_set_bc(pclb_ctx* c, int32_t side, int32_t kind, const double p[4]) {
   c->bc.kind[side] = kind;
   c->bc.neq[side] = neq;
   for (int a = 0; a < 4; ++a) c->bc.p[side][a] = q[a];
+  ++c->stamp;
   return PCLB_OK;
 }
 
@@ -346,6 +372,61 @@ int pclb_step_static(pclb_ctx* c, int64_t n) {
     c->cur = 1 - c->cur;
     ++c->steps;
   }
+  return PCLB_OK;
+}
+
+int pclb_step_graph(pclb_ctx* c, int64_t n) {
+  if (!c) return PCLB_EINVAL;
+  if (!c->bound) return fail(c, PCLB_ESTATE, "bind buffers first");
+  if (n < 0 || n > 100000) return fail(c, PCLB_EINVAL, "step count must be in 0..100000");
+  if (n == 0) return PCLB_OK;
+  hipError_t e = hipSuccess;
+  if (!c->gexec || c->gsteps != n || c->gcur != c->cur || c->gstamp != c->stamp) {
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    if (!c->gstream) {
+      e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(c, e, "capture stream");
+    }
+    // record n steps on the capture stream (nothing runs), buffers alternating
+    // from the current one
+    hipStream_t keep = c->stream;
+    c->stream = c->gstream;
+    e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      c->stream = keep;
+      return hip_fail(c, e, "begin capture");
+    }
+    int cur = c->cur;
+    hipError_t le = hipSuccess;
+    for (int64_t k = 0; k < n && le == hipSuccess; ++k) {
+      le = step_once(c, c->f[cur], c->f[1 - cur], c->d_ghost);
+      cur = 1 - cur;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->gstream, &g);
+    c->stream = keep;
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(c, le, "step launch under capture");
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return hip_fail(c, e, "graph instantiate");
+    }
+    c->gsteps = n;
+    c->gcur = c->cur;
+    c->gstamp = c->stamp;
+  }
+  e = hipGraphLaunch(c->gexec, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+  if (n & 1) c->cur = 1 - c->cur;
+  c->steps += n;
   return PCLB_OK;
 }
 

@@ -121,6 +121,11 @@ class Sim:
     def step(self, n: int = 1):
         N.check(self.L.pclb_step(self.ctx, int(n)), self.ctx)
 
+    def step_graph(self, n: int):
+        """n steps as one replay of a captured HIP graph (same result as
+        step(n)); worth it where kernel launches dominate a step."""
+        N.check(self.L.pclb_step_graph(self.ctx, int(n)), self.ctx)
+
     def step_into(self, f_in: torch.Tensor, f_out: torch.Tensor):
         self._check_state_tensor(f_in)
         self._check_state_tensor(f_out)

@@ -52,9 +52,9 @@ def problem(ni, nf, nr, nth, bc, seed):
                            bc_par=(bc[0][1], bc[1][1]), nf=nf, ni=ni)
 
 
-def start(P, F, precision, noise_seed, scheme=0, relax=0):
+def start(P, F, precision, noise_seed, scheme=0, relax=0, kernel=0):
     from paper_1302_7104_amd.sim import Sim
-    s = Sim(P, precision=precision, scheme=scheme, relaxation=relax)
+    s = Sim(P, precision=precision, scheme=scheme, relaxation=relax, kernel=kernel)
     s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
     f = O.init_feq(grid_of(P, scheme, relax), **F)
     nz = W.noise(f.shape, 1e-3, noise_seed)
@@ -215,12 +215,13 @@ def test_strip_form_bitwise_equals_node_form(ni, shape):
 
 @pytest.mark.parametrize("ni", [16, 24])
 def test_strip_form_parity(ni):
-    """The default kernel choice on a grid the strip form takes (n_theta =
+    """The strip kernel asked for on a grid the strip form takes (n_theta =
     256: four strips) against the oracle: the strip form for the double
     octagon, the per-node form for the triple."""
+    from paper_1302_7104_amd import _native as N
     P, F = problem(ni, ni, 10, 256, BCS[1], 11)
     for prec, tol in ((64, FP64_TOL), (32, FP32_TOL)):
-        s, f0 = start(P, F, prec, 12)
+        s, f0 = start(P, F, prec, 12, kernel=N.KERNEL_STRIP)
         s.step(5)
         got = s.state.double().cpu().numpy()
         want, bad = O.step(grid_of(P), f0, 5)

@@ -294,7 +294,7 @@ def test_node_and_strip_kernels_bitwise_equal():
     for prec in (32, 64):
         P, F = W.kelvin_helmholtz(48, 2048, 10)
         res = []
-        for kernel in (N.KERNEL_NODE, N.KERNEL_AUTO):
+        for kernel in (N.KERNEL_NODE, N.KERNEL_STRIP):
             s = sim_of(P, prec, kernel)
             s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
             s.step(10)
