@@ -600,8 +600,9 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
       eq_models<NI>(rho, ux, uy, E, ec);
       const size_t c0 = (size_t)i * nth + j;
       if (rest) out[c0] = relax_rest<R>(relax_rest_share(ec, ome), e, rcur);
-      const typename Pair2<R>::T H1v = hcur, H2v = hcur;
-      const R H1 = left_lane ? H1v.y : H1v.x, H2 = left_lane ? H2v.x : H2v.y;
+      // halo by role: H1 the column next to the strip (j0 - 1 / j0 + 64), H2
+      // the one beyond it (j0 - 2 / j0 + 65)
+      const R H1 = left_lane ? hcur.y : hcur.x, H2 = left_lane ? hcur.x : hcur.y;
       const R rinv = (R)T.rinv[i];
       const R at = at0 * rinv;
       const double pd = ux * cd + uy * sd;
