@@ -179,12 +179,16 @@ __global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restric
   eq_setup(T, rho, ux, uy, E, ec);
   const double ct = T.cth[j], st = T.sth[j];
   const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
-  // one kind at a time (12 accumulators live, not 48): M, M*, Delta, Delta*
+  // one kind at a time (12 accumulators live, not 48): M, M*, Delta, Delta*;
+  // f^eq is subtracted from the node's values once, before the Delta kinds
   int slot = 0;
 #pragma unroll 1
   for (int kind = 0; kind < 4; ++kind) {
+    if (kind == 2 && (kinds & 12)) {               // from here on the moments of f - f^eq
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) fl[q] -= q == 0 ? ec.rF[0] * ec.A0 : eq_val(ec, k_of(q), d_of(q));
+    }
     if (!((kinds >> kind) & 1)) continue;
-    const bool dev = kind >= 2;                    // moments of f - f^eq
     const double sr = (kind & 1) ? ur : 0.0;       // central: velocities relative to u
     const double sq = (kind & 1) ? ut : 0.0;
     double o[12];
@@ -192,8 +196,7 @@ __global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restric
     for (int c = 0; c < 12; ++c) o[c] = 0.0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const double feq = q == 0 ? ec.rF[0] * ec.A0 : eq_val(ec, k_of(q), d_of(q));
-      const double w = dev ? fl[q] - feq : fl[q];
+      const double w = fl[q];
       const double a = vx_q(q) * ct + vy_q(q) * st - sr;
       const double b = -vx_q(q) * st + vy_q(q) * ct - sq;
       const double h = 0.5 * (a * a + b * b);
