@@ -330,6 +330,29 @@ def test_strip_launch_shapes_bitwise_equal_node_kernel(shape):
             assert np.array_equal(got, want), (shape, prec, chunk, order)
 
 
+@pytest.mark.parametrize("bc", BCS + BCS_NEQ)
+def test_strip_kernels_bitwise_equal_node_kernel_every_boundary(bc):
+    """Both strip kernels (FP32 and FP64) against the node kernel, bit for
+    bit, for every radial boundary kind, the non-equilibrium ghosts included
+    (the strip kernels read the ghost layers the same ghost kernel writes),
+    with chunks of 3 and 64 rows and the default."""
+    from paper_1302_7104_amd import _native as N
+    P, F = smooth_problem(21, 192, bc, 19)
+    for prec in (32, 64):
+        s, _ = start(P, F, prec, noise_seed=20, kernel=N.KERNEL_NODE)
+        f0 = s.state.clone()
+        s.step(6)
+        want = s.state.cpu().numpy()
+        s.close()
+        for chunk in (0, 3, 64):
+            t = sim_of(P, prec, N.KERNEL_STRIP, strip_chunk=chunk)
+            t.load_state(f0)
+            t.step(6)
+            got = t.state.cpu().numpy()
+            t.close()
+            assert np.array_equal(got, want), (bc, prec, chunk)
+
+
 def test_init_rejects_bad_fields():
     from paper_1302_7104_amd._native import PclbError
     P, F = smooth_problem(8, 16, BCS[0], 6)
