@@ -228,8 +228,8 @@ def rm_sector_runs(W, Sim):
 def adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, precision):
     """J = sum over 1.1 < r < 1.5 of rho^2 r dr dtheta after `steps` steps of
     the Richtmyer-Meshkov recipe, and dJ/da_k through the hand-written
-    adjoint with checkpoint-recompute.  Returns (J, grad, forward ms/step,
-    backward ms/step)."""
+    adjoint with checkpoint-recompute (ckpt = 0: every state kept).
+    Returns (J, grad, forward ms/step, backward ms/step)."""
     sim = Sim(P, precision=precision)
     dev = sim.device
     amps = torch.as_tensor(W.rm_amplitudes(1), device=dev).requires_grad_(True)
@@ -285,6 +285,9 @@ def run_adjoint(W, torch, steps=200, ckpt=20):
     P, _ = W.richtmyer_meshkov(1024, 2048, steps)
     J32, g32, fwd32, bwd32 = adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, 32)
     J64, g64, fwd64, bwd64 = adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, ckpt, 64)
+    # every state kept in HBM by the forward: the backward pass without recompute
+    _, g32s, _, bwd32s = adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, 0, 32)
+    _, g64s, _, bwd64s = adjoint_gradient(W, torch, Sim, Evolve, InitState, P, steps, 0, 64)
 
     def rel(a, b):
         return float(np.abs(a - b).max() / np.abs(b).max())
@@ -303,7 +306,11 @@ def run_adjoint(W, torch, steps=200, ckpt=20):
                 fp64_ms_forward_step=fwd64, fp64_ms_backward_per_step=bwd64,
                 fp64_adjoint_over_forward=bwd64 / fwd64,
                 J_fp32=J32, J_fp64=J64, dJ_da_fp32=g32.tolist(), dJ_da_fp64=g64.tolist(),
-                fp32_vs_fp64_gradient=rel(g32, g64), finite_differences=fd)
+                fp32_vs_fp64_gradient=rel(g32, g64), finite_differences=fd,
+                stored_trajectory=dict(
+                    ms_backward_per_step=bwd32s, adjoint_over_forward=bwd32s / fwd32,
+                    fp64_ms_backward_per_step=bwd64s, fp64_adjoint_over_forward=bwd64s / fwd64,
+                    same_gradients=bool(np.array_equal(g32s, g32) and np.array_equal(g64s, g64))))
 
 
 def adjoint_kernel_times(W, torch, steps=50):

@@ -544,6 +544,12 @@ def test_evolve_checkpointing_matches_stored_trajectory():
         s.adjoint_step(states[t], lam, out)
         lam, out = out, lam
     assert torch.equal(got, lam)
+    # the same with every state kept by the forward (no recompute)
+    x2 = f0.clone().requires_grad_(True)
+    fn = Evolve.apply(s, x2, 23, 0)
+    assert torch.equal(fn, states[-1])
+    fn.backward(g_out)
+    assert torch.equal(x2.grad, lam)
 
 
 def test_fd_matches_fp64_adjoint_gradient():
