@@ -282,7 +282,13 @@ int pclb_noneq(pclb_ctx* ctx, const void* f, int32_t kinds, double* out);
  * both upwind differences vanish the derivatives of
  * (delta - delta')|delta|/(|delta|+|delta'|) with respect to (delta, delta')
  * are (1, 0).  All three buffers hold the context's element type and do
- * not overlap.  Asynchronous. */
+ * not overlap.  Asynchronous.  Float states of the full annulus with
+ * n_theta a multiple of 64 take a strip form of the adjoint where the
+ * context's kernel choice would take the strip kernel for pclb_step
+ * (PCLB_KERNEL_STRIP, or PCLB_KERNEL_AUTO on a large enough grid; default
+ * chunk 64 rows); it rounds the products of derivatives and cotangents to
+ * float before summing them, so its result may differ from the node
+ * kernel's by an ulp or two of float. */
 int pclb_adjoint_step(pclb_ctx* ctx, const void* f_t, const void* lam_next, void* lam_out);
 
 /* Adjoint of pclb_init_state: from lam0 = dJ/df at f = f^eq(fields), write

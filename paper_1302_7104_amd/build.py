@@ -9,7 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpclb.so")
-SOURCES = ["pclb_api.cpp", "k_forward.hip", "k_strip.hip", "k_strip64.hip", "k_adjoint.hip", "k_models.hip"]
+SOURCES = ["pclb_api.cpp", "k_forward.hip", "k_strip.hip", "k_strip64.hip", "k_adjoint.hip", "k_adjoint_strip.hip",
+           "k_models.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -71,13 +71,16 @@ __global__ void __launch_bounds__(128) adjoint_init_kernel(Tables T, const R* __
 
 template <class R>
 hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const void* lam,
-                          void* lam_out, void* ghost, double* gm, double tie, hipStream_t s) {
+                          void* lam_out, void* ghost, double* gm, double tie,
+                          const StripTune& tune, bool strip, hipStream_t s) {
   hipError_t e = launch_ghost<R>(T, bc, f, ghost, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ghost_adjoint_kernel<R>, dim3((T.nth + 127) / 128, 2), dim3(128), 0, s, T, bc,
                      (const R*)f, (const R*)lam, (const R*)ghost, tie, gm);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (strip && adjoint_strip_supported(T, std::is_same<R, float>::value ? 32 : 64))
+    return launch_adjoint_strip<R>(T, f, lam, lam_out, ghost, gm, tie, tune, s);
   const dim3 grid((T.nth + 127) / 128, T.nr);
   if (T.nf == 8)
     hipLaunchKernelGGL((adjoint_node_kernel<R, false>), grid, dim3(128), 0, s, T, (const R*)f,
@@ -98,9 +101,9 @@ hipError_t launch_adjoint_init(const Tables& T, const void* lam, const double* r
 }
 
 template hipError_t launch_adjoint<float>(const Tables&, const BCdev&, const void*, const void*, void*,
-                                          void*, double*, double, hipStream_t);
+                                          void*, double*, double, const StripTune&, bool, hipStream_t);
 template hipError_t launch_adjoint<double>(const Tables&, const BCdev&, const void*, const void*, void*,
-                                           void*, double*, double, hipStream_t);
+                                           void*, double*, double, const StripTune&, bool, hipStream_t);
 template hipError_t launch_adjoint_init<float>(const Tables&, const void*, const double*, const double*,
                                                const double*, const double*, double*, double*, double*,
                                                double*, hipStream_t);

@@ -65,10 +65,17 @@ template <class R>
 hipError_t launch_models_diag(const Tables& T, int ni, const void* f, double* partial, double step,
                               double* out, hipStream_t s);
 
-// Adjoint.
+// Adjoint.  strip: the strip form of the node adjoint where it applies.
 template <class R>
 hipError_t launch_adjoint(const Tables& T, const BCdev& bc, const void* f, const void* lam,
-                          void* lam_out, void* ghost, double* gm, double tie, hipStream_t s);
+                          void* lam_out, void* ghost, double* gm, double tie,
+                          const StripTune& tune, bool strip, hipStream_t s);
+// The strip adjoint (FP32 states, full annulus, MWB, n_theta a multiple of 64).
+bool adjoint_strip_supported(const Tables& T, int precision);
+template <class R>
+hipError_t launch_adjoint_strip(const Tables& T, const void* f, const void* lam, void* lam_out,
+                                const void* ghost, const double* gm, double tie,
+                                const StripTune& tune, hipStream_t s);
 template <class R>
 hipError_t launch_adjoint_init(const Tables& T, const void* lam, const double* rho,
                                const double* ur, const double* ut, const double* Tt, double* d_rho,

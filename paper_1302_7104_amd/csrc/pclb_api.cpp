@@ -520,9 +520,15 @@ int pclb_adjoint_step(pclb_ctx* c, const void* f_t, const void* lam_next, void* 
   if (c->cfg.n_i != 8) return fail(c, PCLB_EINVAL, "the adjoint covers the octagon (n_i = 8) only");
   if (c->bc.neq[0] || c->bc.neq[1])
     return fail(c, PCLB_EINVAL, "the adjoint covers equilibrium ghost layers only (no PCLB_BC_NONEQ)");
+  // the strip form where it applies and, unless asked for, where the grid
+  // gives it enough workgroups
+  const int kern = c->cfg.kernel;
+  const bool strip = kern == PCLB_KERNEL_STRIP || (kern == PCLB_KERNEL_AUTO && strip_pays(c));
   hipError_t e = c->cfg.precision == 32
-                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream)
-                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm, c->tie, c->stream);
+                     ? launch_adjoint<float>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm,
+                                             c->tie, c->tune, strip, c->stream)
+                     : launch_adjoint<double>(c->T, c->bc, f_t, lam_next, lam_out, c->d_ghost, c->d_gm,
+                                              c->tie, c->tune, strip, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
   return PCLB_OK;
 }
