@@ -108,3 +108,25 @@ def test_strip_adjoint_at_the_gradient_configuration():
     err = float(((strip - node).abs() / sc).max())
     print(f"1024 x 2048: max |strip - node| / scale {err:.3e}")
     assert err <= 1e-6, err
+
+
+@pytest.mark.parametrize("nr,nth,chunk", [(20, 64, 0), (4, 64, 0), (5, 128, 2), (6, 64, 1)])
+def test_strip_adjoint_small_grids(nr, nth, chunk):
+    """Edge shapes: one strip (its halo columns are its own, wrapped), fewer
+    rows than the radial stencils reach, one-row chunks."""
+    P, F = smooth_problem(nr, nth, BCS[1], 51)
+    g = grid_of(P)
+    tie = 1e-6
+    f_in, lam_in = inputs(P, F, 52)
+    got = adjoint_of(P, STRIP, f_in, lam_in, tie, chunk)
+    node = adjoint_of(P, NODE, f_in, lam_in, tie)
+    assert np.isfinite(got).all()
+    sc = local_scale(node, lam_in)
+    assert (np.abs(got - node) / sc).max() <= 1e-6
+    w = [O.adjoint_step(g, f_in, lam_in, tie_eps=t * tie) for t in (1.0, 0.99, 1.01)]
+    sc = local_scale(w[0], lam_in)
+    branch = (np.abs(w[1] - w[0]) > 1e-9 * sc) | (np.abs(w[2] - w[0]) > 1e-9 * sc)
+    err = np.where(branch, np.min([np.abs(got - x) for x in w], axis=0), np.abs(got - w[0])) / sc
+    wall = np.zeros((P.nr, P.nth), bool)
+    wall[:2] = wall[-2:] = True
+    assert (err <= np.where(wall[None], 1e-3, 2e-6)).all(), err.max()
