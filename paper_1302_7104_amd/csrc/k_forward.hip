@@ -162,60 +162,137 @@ __global__ void __launch_bounds__(256) fields_kernel(Tables T, const R* __restri
 // theta theta theta; r, theta; rr, r theta, theta theta).  f^eq is summed from
 // the discrete equilibrium of the node's rho, u, E.  All in double.  The kinds
 // selected by the bit mask go to out in the order M, M*, Delta, Delta*.
+//
+// Every component is a moment of order 2 to 4 in the polar velocity
+// components, so the kernel sums the 15 polar moments up to order four once,
+// P[n][m] = sum_q w_q a^(n-m) b^m (a = v . e_r, b = v . e_theta), for w = f
+// and for w = f - f^eq, and forms the central ones from them with the
+// binomial sum over (a - u_r)^i (b - u_theta)^j.  Each rounding is relative to
+// a term of the sum over q of |w_q| (|v_q| + |u|)^order.
+namespace noneq {
+
+constexpr int NM = 15;                                    // moments of order 0..4
+__host__ __device__ constexpr int mo(int n, int m) { return n * (n + 1) / 2 + m; }
+// binomial coefficients C(n, k), n <= 4
+__device__ constexpr double BINOM[5][5] = {
+    {1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0}, {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+
+// P += t w and P_d += t w_d over the 15 monomials t = a^(n-m) b^m
+__device__ __forceinline__ void polar_add(double a, double b, double w, double wd,
+                                          double (&Pf)[NM], double (&Pd)[NM]) {
+  double pa[5], pb[5];
+  pa[0] = pb[0] = 1.0;
+#pragma unroll
+  for (int p = 1; p < 5; ++p) {
+    pa[p] = pa[p - 1] * a;
+    pb[p] = pb[p - 1] * b;
+  }
+#pragma unroll
+  for (int n = 0; n <= 4; ++n)
+#pragma unroll
+    for (int m = 0; m <= n; ++m) {
+      const double t = pa[n - m] * pb[m];
+      Pf[mo(n, m)] += t * w;
+      Pd[mo(n, m)] += t * wd;
+    }
+}
+
+// sum_q w (a - sr)^I (b - st)^J from the polar moments; pr[p] = (-sr)^p,
+// pt[p] = (-st)^p
+template <int I, int J>
+__device__ __forceinline__ double shifted(const double (&P)[NM], const double (&pr)[5],
+                                          const double (&pt)[5]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = I; k >= 0; --k)
+#pragma unroll
+    for (int l = J; l >= 0; --l)
+      acc += (BINOM[I][k] * BINOM[J][l]) * (pr[I - k] * pt[J - l]) * P[mo(k + l, l)];
+  return acc;
+}
+
+// the 12 components of one kind, about (sr, st)
+__device__ __forceinline__ void components(const double (&P)[NM], double sr, double st,
+                                           double (&o)[12]) {
+  double pr[5], pt[5];
+  pr[0] = pt[0] = 1.0;
+#pragma unroll
+  for (int p = 1; p < 5; ++p) {
+    pr[p] = pr[p - 1] * -sr;
+    pt[p] = pt[p - 1] * -st;
+  }
+  const double s20 = shifted<2, 0>(P, pr, pt), s11 = shifted<1, 1>(P, pr, pt), s02 = shifted<0, 2>(P, pr, pt);
+  const double s30 = shifted<3, 0>(P, pr, pt), s21 = shifted<2, 1>(P, pr, pt);
+  const double s12 = shifted<1, 2>(P, pr, pt), s03 = shifted<0, 3>(P, pr, pt);
+  const double s40 = shifted<4, 0>(P, pr, pt), s31 = shifted<3, 1>(P, pr, pt), s22 = shifted<2, 2>(P, pr, pt);
+  const double s13 = shifted<1, 3>(P, pr, pt), s04 = shifted<0, 4>(P, pr, pt);
+  o[0] = s20;  o[1] = s11;  o[2] = s02;
+  o[3] = s30;  o[4] = s21;  o[5] = s12;  o[6] = s03;
+  o[7] = 0.5 * (s30 + s12);   // sum w |c|^2/2 c_r
+  o[8] = 0.5 * (s21 + s03);
+  o[9] = 0.5 * (s40 + s22);   // sum w |c|^2/2 c_r c_r
+  o[10] = 0.5 * (s31 + s13);
+  o[11] = 0.5 * (s22 + s04);
+}
+
+}  // namespace noneq
+
 template <class R>
 __global__ void __launch_bounds__(256) noneq_kernel(Tables T, const R* __restrict__ f, int kinds,
                                                     double* __restrict__ out) {
+  using namespace noneq;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= T.nth) return;
   const size_t plane = (size_t)T.nr * T.nth;
   const size_t c0 = (size_t)i * T.nth + j;
-  double fl[NQ];
+  R fl[NQ];                    // the node's values in the state's type
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) fl[q] = (double)f[q * plane + c0];
+  for (int q = 0; q < NQ; ++q) fl[q] = f[q * plane + c0];
   double rho, ux, uy, E;
-  node_macros(fl, rho, ux, uy, E);
+  {
+    double fd[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fd[q] = (double)fl[q];
+    node_macros(fd, rho, ux, uy, E);
+  }
+  const double f0 = (double)fl[0];
   EqCoef ec;
   eq_setup(T, rho, ux, uy, E, ec);
   const double ct = T.cth[j], st = T.sth[j];
-  const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
-  // one kind at a time (12 accumulators live, not 48): M, M*, Delta, Delta*;
-  // f^eq is subtracted from the node's values once, before the Delta kinds
-  int slot = 0;
+  double Pf[NM], Pd[NM];
+#pragma unroll
+  for (int m = 1; m < NM; ++m) Pf[m] = Pd[m] = 0.0;
+  Pf[0] = f0;                                   // the rest velocity: order 0 only
+  Pd[0] = f0 - ec.rF[0] * ec.A0;
+  // speeds in a loop (a bounded working set: unrolled, the scheduler keeps
+  // every velocity's products live at once), directions unrolled
 #pragma unroll 1
+  for (int k = 1; k <= NK; ++k) {
+    const double vk = k == 1 ? speed(1) : k == 2 ? speed(2) : k == 3 ? speed(3) : speed(4);
+    const double rFk = k == 1 ? ec.rF[1] : k == 2 ? ec.rF[2] : k == 3 ? ec.rF[3] : ec.rF[4];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double w = (double)(k == 1 ? fl[1 + d] : k == 2 ? fl[9 + d] : k == 3 ? fl[17 + d] : fl[25 + d]);
+      const double x = vk * (d < 4 ? ec.p[d] : -ec.p[d - 4]);
+      const double fe = rFk * (ec.A0 + x * (ec.A1 + x * (ec.A2 + x * (ec.A3 + x * ec.A4))));
+      // polar components of e_d at this node, times the speed
+      const double ea = cos_d(d) * ct + sin_d(d) * st, eb = sin_d(d) * ct - cos_d(d) * st;
+      polar_add(vk * ea, vk * eb, w, w - fe, Pf, Pd);
+    }
+  }
+  const double ur = ux * ct + uy * st, ut = -ux * st + uy * ct;
+  int slot = 0;
+#pragma unroll
   for (int kind = 0; kind < 4; ++kind) {
-    if (kind == 2 && (kinds & 12)) {               // from here on the moments of f - f^eq
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) fl[q] -= q == 0 ? ec.rF[0] * ec.A0 : eq_val(ec, k_of(q), d_of(q));
-    }
     if (!((kinds >> kind) & 1)) continue;
-    const double sr = (kind & 1) ? ur : 0.0;       // central: velocities relative to u
-    const double sq = (kind & 1) ? ut : 0.0;
+    const bool central = kind & 1;
     double o[12];
+    if (kind < 2) components(Pf, central ? ur : 0.0, central ? ut : 0.0, o);
+    else components(Pd, central ? ur : 0.0, central ? ut : 0.0, o);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) o[c] = 0.0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double w = fl[q];
-      const double a = vx_q(q) * ct + vy_q(q) * st - sr;
-      const double b = -vx_q(q) * st + vy_q(q) * ct - sq;
-      const double h = 0.5 * (a * a + b * b);
-      const double wa = w * a, wb = w * b, waa = wa * a, wab = wa * b, wbb = wb * b;
-      o[0] += waa;
-      o[1] += wab;
-      o[2] += wbb;
-      o[3] += waa * a;
-      o[4] += waa * b;
-      o[5] += wab * b;
-      o[6] += wbb * b;
-      o[7] += h * wa;
-      o[8] += h * wb;
-      o[9] += h * waa;
-      o[10] += h * wab;
-      o[11] += h * wbb;
-    }
-#pragma unroll
-    for (int c = 0; c < 12; ++c) out[((size_t)slot * 12 + c) * plane + c0] = o[c];
+    for (int c = 0; c < 12; ++c)   // not read again here: nontemporal
+      __builtin_nontemporal_store(o[c], out + ((size_t)slot * 12 + c) * plane + c0);
     ++slot;
   }
 }
