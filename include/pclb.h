@@ -79,8 +79,11 @@ enum {
  * double form runs double states of the full annulus with the MWB scheme and
  * n_theta a multiple of 64.  Everything else (sectors, the comparison
  * schemes, other grids) runs on the node kernel, whatever is asked.  The
- * double and triple octagon run on a kernel of their own (one thread per
- * node, velocities in a loop) whatever is asked. */
+ * double and triple octagon have kernels of their own: a strip form for the
+ * double octagon and for float states of the triple octagon on the full
+ * annulus with the MWB scheme and n_theta a multiple of 64 (chosen as above),
+ * and a per-node form (one thread per node, velocities in a loop) for
+ * everything else; both give the same result bit for bit. */
 enum {
   PCLB_KERNEL_AUTO = 0,    /* the strip kernel when the grid allows it and gives it at least
                               512 workgroups (64-column strips times chunks of 8 rows), else

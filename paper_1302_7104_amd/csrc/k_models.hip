@@ -474,9 +474,11 @@ __global__ void __launch_bounds__(DIAG_BLOCK) models_diag_kernel(Tables T, const
 // pairs: a workgroup of N_i/2 wavefronts owns a strip of 64 theta columns
 // (one per lane) and marches in r over a chunk of rows; wave W owns the pair
 // (W, W + N_i/2), eight velocities, and wave 0 also the rest velocity.  Each
-// owned velocity keeps six rows in registers (i-2 .. i+3 at row i; the load
-// of a row is issued two rows before its first use, the row loop unrolled
-// six times so the roles rotate at compile time).  Per row the waves
+// owned velocity keeps a ring of MS_RING rows in registers: six (i-2 .. i+3
+// at row i, the load of a row issued two rows before its first use) for the
+// double octagon, five (i-2 .. i+2, one row before) for the triple octagon,
+// whose twelve waves have 168 registers each; the row loop is unrolled
+// MS_RING times so the roles rotate at compile time.  Per row the waves
 // exchange their pair partials through LDS (one barrier, double-buffered by
 // row parity), each builds the node's equilibrium from their sum in pair
 // order, and updates its velocities with the node kernel's arithmetic, so the
@@ -484,7 +486,6 @@ __global__ void __launch_bounds__(DIAG_BLOCK) models_diag_kernel(Tables T, const
 // lanes (ds_bpermute); the two columns beyond each end of the strip from a
 // halo read one row ahead (one load per lane: lane v the pair left of the
 // strip for velocity v, lane 8 + v the pair right of it).
-constexpr int MS_RING = 6;
 
 template <class R> struct Pair2;
 template <> struct Pair2<float> { using T = float2; };
@@ -503,7 +504,7 @@ __device__ inline double ms_pick(uint64_t m, double a, double b) {
 
 // d: this wave's direction pair (wave-uniform; one copy of the code serves
 // every wave, so that no wave holds another's values)
-template <class R, int NI>
+template <class R, int NI, int MS_RING>
 __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __restrict__ out,
                                 const R* __restrict__ ghost, int d, int j0, int i0, int i1,
                                 double* lds) {
@@ -629,8 +630,8 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
           out[qv(v) * plane + c0] = (R)((rel[h] - (double)tr) - (double)tt);
         }
       });
-      // look-ahead: row i + 4 into the slot of row i - 2
-      const int row = i + 4;
+      // look-ahead: row i + MS_RING - 2 into the slot of row i - 2
+      const int row = i + MS_RING - 2;
       if (row <= last) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) S[u % MS_RING][v] = load(v, row);
@@ -639,7 +640,7 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
   }
 }
 
-template <class R, int NI>
+template <class R, int NI, int RING>
 __global__ void __launch_bounds__(64 * (NI / 2))
 models_strip_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
                     const R* __restrict__ ghost, int chunk) {
@@ -649,7 +650,8 @@ models_strip_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
   const int strip_i = item % nstrip, ck = item / nstrip;
   const int j0 = strip_i * 64;
   const int i0 = ck * chunk, i1 = min(i0 + chunk, T.nr);
-  ms_march<R, NI>(T, f, out, ghost, __builtin_amdgcn_readfirstlane(threadIdx.x / 64), j0, i0, i1, lds);
+  ms_march<R, NI, RING>(T, f, out, ghost, __builtin_amdgcn_readfirstlane(threadIdx.x / 64), j0, i0, i1,
+                        lds);
 }
 
 }  // namespace
@@ -683,24 +685,30 @@ void launch_models_step_ni(const Tables& T, dim3 grid, const R* f, R* out, const
   }
 }
 
-// The strip form serves the double octagon.  For the triple octagon its
-// twelve waves per workgroup must fit in 168 registers each, which spills
-// the ring (FP32 12.9 ms against 11.8 for the per-node form at 4096 x 8192,
-// FP64 34 ms against 18), so it keeps the per-node form.
-bool models_strip_supported(const Tables& T, int ni) {
-  return ni == 16 && T.nf == ni && T.scheme == SCH_MWB && T.nth >= 64 && T.nth % 64 == 0;
+// The strip form serves the double octagon (six-row ring) and float states of
+// the triple octagon, whose twelve waves per workgroup must fit in 168
+// registers each: with a five-row ring (the look-ahead row issued one row
+// before its first use) the float form does; the double form spills.
+bool models_strip_supported(const Tables& T, int ni, int precision) {
+  return (ni == 16 || (ni == 24 && precision == 32)) && T.nf == ni && T.scheme == SCH_MWB &&
+         T.nth >= 64 && T.nth % 64 == 0;
 }
 
 template <class R>
 hipError_t launch_models_step(const Tables& T, int ni, const void* f, void* out, const void* ghost,
                               const StripTune& tune, bool strip, hipStream_t s) {
-  if (strip && models_strip_supported(T, ni)) {   // ni == 16
+  constexpr int prec = std::is_same<R, float>::value ? 32 : 64;
+  if (strip && models_strip_supported(T, ni, prec)) {
     int chunk = tune.chunk > 0 ? tune.chunk : 32;
     const int strips = T.nth / 64;
     while (tune.chunk <= 0 && chunk > 8 && (long)strips * ((T.nr + chunk - 1) / chunk) < 4096) chunk /= 2;
     const dim3 grid(strips * ((T.nr + chunk - 1) / chunk));
-    hipLaunchKernelGGL((models_strip_kernel<R, 16>), grid, dim3(64 * 8), 0, s, T, (const R*)f, (R*)out,
-                       (const R*)ghost, chunk);
+    if (ni == 16)
+      hipLaunchKernelGGL((models_strip_kernel<R, 16, 6>), grid, dim3(64 * 8), 0, s, T, (const R*)f,
+                         (R*)out, (const R*)ghost, chunk);
+    else if constexpr (prec == 32)
+      hipLaunchKernelGGL((models_strip_kernel<R, 24, 5>), grid, dim3(64 * 12), 0, s, T, (const R*)f,
+                         (R*)out, (const R*)ghost, chunk);
     return hipGetLastError();
   }
   const dim3 grid((T.nth + 255) / 256, T.nr);
