@@ -85,9 +85,10 @@ def run_forward(W, Sim, torch, precision, steps, warmup, nr=4096, nth=8192):
 
 def run_variants(W, Sim, torch, steps=20, warmup=3):
     """FP32 step time on the headline workload for each convection scheme and
-    relaxation form (the comparison schemes run on the node kernel, MWB on
-    the strip kernel and, for reference, on the node kernel), and the time of
-    the non-equilibrium fields kernel (all four kinds) on the same state."""
+    relaxation form (MWB and the two upwind comparison schemes on the strip
+    kernel, Lax-Wendroff on the node kernel, MWB also on the node kernel for
+    reference), and the time of the non-equilibrium fields kernel (all four
+    kinds) on the same state."""
     import ctypes
     from paper_1302_7104_amd import _native as N
     P, F = W.kelvin_helmholtz(4096, 8192, steps)
@@ -96,9 +97,9 @@ def run_variants(W, Sim, torch, steps=20, warmup=3):
     out = {}
     variants = (("mwb_strip", {}), ("mwb_node", {"kernel": N.KERNEL_NODE}),
                 ("mwb_euler_relaxation_strip", {"relaxation": N.RELAX_EULER}),
-                ("warming_beam_node", {"scheme": N.SCHEME_WB}),
+                ("warming_beam_strip", {"scheme": N.SCHEME_WB}),
                 ("lax_wendroff_node", {"scheme": N.SCHEME_LW}),
-                ("upwind2_node", {"scheme": N.SCHEME_UPWIND2}))
+                ("upwind2_strip", {"scheme": N.SCHEME_UPWIND2}))
     for name, kw in variants:
         sim = Sim(P, precision=32, **kw)
         sim.init_state(F["rho"], F["ur"], F["ut"], F["T"])

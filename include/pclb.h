@@ -72,13 +72,14 @@ enum {
 
 /* Kernel selection for pclb_step / pclb_step_into.  Both kernels give the
  * same result bit for bit.  The strip kernel runs float states of the full
- * annulus (n_f = 8) with the MWB scheme and n_theta >= 64 whose planes it can
- * address with 32-bit offsets; its strips of 64 columns that straddle an
- * octant boundary theta = m pi/4 (none when n_theta is a multiple of 512) run
- * in a second launch of a variant that selects upwind sides per lane.  Its
- * double form runs double states of the full annulus with the MWB scheme and
- * n_theta a multiple of 64.  Everything else (sectors, the comparison
- * schemes, other grids) runs on the node kernel, whatever is asked.  The
+ * annulus (n_f = 8) with an upwind scheme (MWB, Warming-Beam, second-order
+ * upwind) and n_theta >= 64 whose planes it can address with 32-bit offsets;
+ * its strips of 64 columns that straddle an octant boundary theta = m pi/4
+ * (none when n_theta is a multiple of 512) run in a second launch of a
+ * variant that selects upwind sides per lane.  Its double form runs double
+ * states of the full annulus with an upwind scheme and n_theta a multiple of
+ * 64.  Everything else (sectors, Lax-Wendroff, other grids) runs on the node
+ * kernel, whatever is asked.  The
  * double and triple octagon have kernels of their own: a strip form for the
  * double octagon and for float states of the triple octagon on the full
  * annulus with the MWB scheme and n_theta a multiple of 64 (chosen as above),
@@ -93,8 +94,10 @@ enum {
 };
 
 /* Convection scheme (pclb_config.scheme): the paper's MWB scheme and the three
- * it is compared with (Sec. II.B; Sec. III.A, Figs. 5 and 6).  Only MWB runs on
- * the strip kernel and has an adjoint. */
+ * it is compared with (Sec. II.B; Sec. III.A, Figs. 5 and 6).  MWB,
+ * Warming-Beam and second-order upwind run on the strip kernels (Lax-Wendroff,
+ * whose stencil reaches downwind, on the node kernel); only MWB has an
+ * adjoint. */
 enum {
   PCLB_SCHEME_MWB = 0,     /* Eq. MWB Scheme with S(eta) = (|eta| - 1) / (|eta| + 1) */
   PCLB_SCHEME_WB = 1,      /* Warming-Beam, Eq. WB_Scheme_1 */

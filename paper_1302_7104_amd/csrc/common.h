@@ -396,13 +396,33 @@ PCLB_HD inline R mwb_update_d(double rel, R aCr, R Kr, R d1r, R d2r, R aCt, R Kt
 //   Lax-Wendroff:        aC d1 + K/2 (dw - d1)
 //   second-order upwind: aC d1 + aC/2 (d1 - d2)
 // (each equals the scheme's printed or textbook form for either sign of C).
+// The upwind schemes' term from the differences alone (not Lax-Wendroff).
+template <int SCH, class R>
+PCLB_HD inline R conv_term_d(R aC, R K, R d1, R d2) {
+  static_assert(SCH != SCH_LW, "Lax-Wendroff needs the downwind neighbour");
+  if constexpr (SCH == SCH_WB) return aC * d1 + (R)0.5 * K * (d1 - d2);
+  else if constexpr (SCH == SCH_UPWIND2) return aC * d1 + (R)0.5 * aC * (d1 - d2);
+  else return aC * d1 + K * mwb_lim<R>(d1, d2);
+}
+
 template <int SCH, class R>
 PCLB_HD inline R conv_term(R aC, R K, R c, R u1, R u2, R w1) {
   const R d1 = c - u1, d2 = u1 - u2;
-  if constexpr (SCH == SCH_WB) return aC * d1 + (R)0.5 * K * (d1 - d2);
-  else if constexpr (SCH == SCH_LW) return aC * d1 + (R)0.5 * K * ((w1 - c) - d1);
-  else if constexpr (SCH == SCH_UPWIND2) return aC * d1 + (R)0.5 * aC * (d1 - d2);
-  else return aC * d1 + K * mwb_lim<R>(d1, d2);
+  if constexpr (SCH == SCH_LW) return aC * d1 + (R)0.5 * K * ((w1 - c) - d1);
+  else return conv_term_d<SCH, R>(aC, K, d1, d2);
+}
+
+// rel - T_r - T_theta of an upwind scheme from the differences, as
+// mwb_update_d (the same rounding as velocity_update for that scheme).
+template <int SCH, class R>
+PCLB_HD inline R scheme_update_d(double rel, R aCr, R Kr, R d1r, R d2r, R aCt, R Kt, R d1t, R d2t) {
+  if constexpr (SCH == SCH_MWB) {
+    return mwb_update_d<R>(rel, aCr, Kr, d1r, d2r, aCt, Kt, d1t, d2t);
+  } else {
+    const R tr = conv_term_d<SCH, R>(aCr, Kr, d1r, d2r);
+    const R tt = conv_term_d<SCH, R>(aCt, Kt, d1t, d2t);
+    return (R)((rel - (double)tr) - (double)tt);
+  }
 }
 
 // The same from the centre value c and the upwind neighbours.

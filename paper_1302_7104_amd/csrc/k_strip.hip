@@ -12,7 +12,10 @@
 //
 // Per row: moments, equilibrium and analytic relaxation in double (Eqs.
 // moment1-3, F_k, feq, operator1_new), the radial and azimuthal MWB terms in
-// float, one store per velocity, the look-ahead loads.
+// float, one store per velocity, the look-ahead loads.  The kernel is
+// templated on the convection scheme: the two upwind schemes the paper
+// compares MWB with (Warming-Beam and second-order upwind) use the same
+// stencil and differences, with their own terms (conv_term_d).
 //
 // Register slots by role.  The radial velocity components of the opposite
 // directions d and d+4 have opposite signs, so on almost every strip one
@@ -152,7 +155,7 @@ __device__ inline void load_halo(const StripCtx& X, uint32_t soff, int row, bool
 // read with one load for all slots at the start of the row (hp: lane v's
 // pointer to that pair in row 0), and each slot takes its pair with
 // readlane.  Mixed waves keep one pair of registers per slot (HA, HB).
-template <int NSPLIT, int W, bool EDGE, bool UNI, int NS>
+template <int NSPLIT, int W, bool EDGE, bool UNI, int NS, int SCH>
 __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                  const Roles<4 / NSPLIT>& RL, int i, int ir, float rinv_lane,
                                  bool more, bool moreN, const int* ta,
@@ -272,7 +275,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
       }
       const float u1r = B[v];
       const float d1r = c - u1r, d2r = u1r - (bk ? A[v] : C[v]);
-      const float res = mwb_update_d<float>(rl, aCr, Kr, d1r, d2r, aCt, Kt, d1t, d2t);
+      const float res = scheme_update_d<SCH, float>(rl, aCr, Kr, d1r, d2r, aCt, Kt, d1t, d2t);
       store_slot<k>(X, RL.soff[pl][h], ovoff, res);
       A[v] = load_slot<EDGE, k>(X, RL.soff[pl][h], RL.qb[pl][h], bk ? i + NS - 2 : i + NS,
                                 bk ? vb : vf, moreN);
@@ -287,7 +290,7 @@ __device__ inline void strip_row(const Tables& T, const StripCtx& X, const DirGe
   }
 }
 
-template <int NSPLIT, int W, bool EDGE, bool UNI, int NS>
+template <int NSPLIT, int W, bool EDGE, bool UNI, int NS, int SCH>
 __device__ inline void strip_march(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                    const Roles<4 / NSPLIT>& RL, int i_begin, int i_end,
                                    double* lds) {
@@ -355,7 +358,7 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
       for_v<0, NS>([&](auto uc) {
         constexpr int u = decltype(uc)::value;
         const int iu = i + u;
-        strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
+        strip_row<NSPLIT, W, EDGE, UNI, NS, SCH>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
                                             iu + 1 < i_end, iu + NS - 2 < i_end, ta, r0,
                                             S[u % NS], S[(u + 1) % NS], S[(u + 2) % NS], HA, HB,
                                             hlo, hhi, hp, lds);
@@ -365,7 +368,7 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
       constexpr int u = decltype(uc)::value;
       const int iu = i + u;
       if (iu < i_end)
-        strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
+        strip_row<NSPLIT, W, EDGE, UNI, NS, SCH>(T, X, G, RL, iu, iu - i_begin, rinv_lane,
                                             iu + 1 < i_end, iu + NS - 2 < i_end, ta, r0,
                                             S[u % NS], S[(u + 1) % NS], S[(u + 2) % NS], HA, HB,
                                             hlo, hhi, hp, lds);
@@ -374,7 +377,7 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
     // one row per iteration, the ring rotated by register moves (its loads
     // are one row ahead and waited for at the next row's start anyway)
     for (int i = i_begin; i < i_end; ++i) {
-      strip_row<NSPLIT, W, EDGE, UNI, NS>(T, X, G, RL, i, i - i_begin, rinv_lane, i + 1 < i_end,
+      strip_row<NSPLIT, W, EDGE, UNI, NS, SCH>(T, X, G, RL, i, i - i_begin, rinv_lane, i + 1 < i_end,
                                           i + 1 < i_end, ta, r0,
                                           S[0], S[1], S[2], HA, HB, hlo, hhi, hp, lds);
       for_v<0, O::NV>([&](auto vc) {
@@ -388,7 +391,7 @@ __device__ inline void strip_march(const Tables& T, const StripCtx& X, const Dir
   }
 }
 
-template <int NSPLIT, int W, bool MIXED, int NS = MIXED ? 3 : 4>
+template <int NSPLIT, int W, bool MIXED, int SCH, int NS = MIXED ? 3 : 4>
 __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirGeom<float>& G,
                                   int i_begin, int i_end, double* lds) {
   using O = Own<NSPLIT, W>;
@@ -426,13 +429,13 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
   const bool all_uni = __syncthreads_and(uni ? 1 : 0) != 0;
   if (all_uni == MIXED) return;
   if constexpr (!MIXED) {
-    if (edge) strip_march<NSPLIT, W, true, true, NS>(T, X, G, RL, i_begin, i_end, lds);
-    else strip_march<NSPLIT, W, false, true, NS>(T, X, G, RL, i_begin, i_end, lds);
+    if (edge) strip_march<NSPLIT, W, true, true, NS, SCH>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, true, NS, SCH>(T, X, G, RL, i_begin, i_end, lds);
     return;
   }
   if (uni) {
-    if (edge) strip_march<NSPLIT, W, true, true, NS>(T, X, G, RL, i_begin, i_end, lds);
-    else strip_march<NSPLIT, W, false, true, NS>(T, X, G, RL, i_begin, i_end, lds);
+    if (edge) strip_march<NSPLIT, W, true, true, NS, SCH>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, true, NS, SCH>(T, X, G, RL, i_begin, i_end, lds);
   } else {
 #pragma unroll
     for (int pl = 0; pl < O::D4N; ++pl) {       // mixed: members in natural order
@@ -445,8 +448,8 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
         RL.tb[pl][h] = false;
       }
     }
-    if (edge) strip_march<NSPLIT, W, true, false, NS>(T, X, G, RL, i_begin, i_end, lds);
-    else strip_march<NSPLIT, W, false, false, NS>(T, X, G, RL, i_begin, i_end, lds);
+    if (edge) strip_march<NSPLIT, W, true, false, NS, SCH>(T, X, G, RL, i_begin, i_end, lds);
+    else strip_march<NSPLIT, W, false, false, NS, SCH>(T, X, G, RL, i_begin, i_end, lds);
   }
 }
 
@@ -455,7 +458,7 @@ __device__ inline void strip_wave(const Tables& T, const StripCtx& X, const DirG
 // Two waves per SIMD (at most 256 registers per lane): left to itself the
 // compiler spends a few accumulation registers beyond that on the uniform
 // variant and drops to one wave.
-template <int NSPLIT, bool MIXED>
+template <int NSPLIT, bool MIXED, int SCH>
 __global__ void __launch_bounds__(WAVE * NSPLIT) __attribute__((amdgpu_waves_per_eu(2)))
 step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out,
                   const float* __restrict__ ghost, int chunk_rows, int n_strips, int xcd_order) {
@@ -509,15 +512,15 @@ step_strip_kernel(Tables T, const float* __restrict__ f, float* __restrict__ out
   DirGeom<float> G;
   dir_geometry(T.cth[X.col], T.sth[X.col], octant_of(X.col, nth, T.nf), T.dt_dr, T.dt_dth, G);
   if constexpr (NSPLIT == 1) {
-    strip_wave<1, 0, MIXED>(T, X, G, i_begin, i_end, lds);
+    strip_wave<1, 0, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
   } else if constexpr (NSPLIT == 2) {
-    if (w == 0) strip_wave<2, 0, MIXED>(T, X, G, i_begin, i_end, lds);
-    else strip_wave<2, 1, MIXED>(T, X, G, i_begin, i_end, lds);
+    if (w == 0) strip_wave<2, 0, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
+    else strip_wave<2, 1, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
   } else {
-    if (w == 0) strip_wave<4, 0, MIXED>(T, X, G, i_begin, i_end, lds);
-    else if (w == 1) strip_wave<4, 1, MIXED>(T, X, G, i_begin, i_end, lds);
-    else if (w == 2) strip_wave<4, 2, MIXED>(T, X, G, i_begin, i_end, lds);
-    else strip_wave<4, 3, MIXED>(T, X, G, i_begin, i_end, lds);
+    if (w == 0) strip_wave<4, 0, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
+    else if (w == 1) strip_wave<4, 1, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
+    else if (w == 2) strip_wave<4, 2, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
+    else strip_wave<4, 3, MIXED, SCH>(T, X, G, i_begin, i_end, lds);
   }
 }
 
@@ -528,8 +531,10 @@ bool strip_supported(const Tables& T) {
   // marker; the lanes of one strip must be distinct columns
   const double plane_bytes = 4.0 * T.nr * (double)T.nth;
   // the strip kernel wraps theta without rotating the velocity index (full
-  // annulus only) and carries the MWB scheme only
-  return std::is_same<R, float>::value && T.nf == 8 && T.scheme == SCH_MWB && T.nth >= WAVE &&
+  // annulus only) and carries the upwind schemes (MWB, Warming-Beam and
+  // second-order upwind), not Lax-Wendroff, whose downwind neighbour its
+  // ring does not hold
+  return std::is_same<R, float>::value && T.nf == 8 && T.scheme != SCH_LW && T.nth >= WAVE &&
          9.0 * plane_bytes < 2147483647.0;
 }
 
@@ -558,6 +563,24 @@ int strip_mixed_count(int nth, int nf) {
   return n;
 }
 
+// strips whose waves are all uniform, then (if any strip straddles an octant
+// boundary, or has its halo columns apart) the others, in a second launch
+// over the same grid in which the uniform strips return at once
+template <int SCH>
+hipError_t launch_strip_sch(const Tables& T, const float* fi, float* fo, const float* gh, int chunk_rows,
+                            int strips, int order, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((step_strip_kernel<2, false, SCH>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo,
+                     gh, chunk_rows, strips, order);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (T.n_mixed > 0 || T.nth % 2 != 0) {
+    hipLaunchKernelGGL((step_strip_kernel<2, true, SCH>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo,
+                       gh, chunk_rows, strips, order);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 template <class R>
 hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const void* ghost,
                              const StripTune& tune, hipStream_t s) {
@@ -571,19 +594,12 @@ hipError_t launch_step_strip(const Tables& T, const void* f, void* out, const vo
   const float* fi = (const float*)f;
   float* fo = (float*)out;
   const float* gh = (const float*)ghost;
-  // strips whose waves are all uniform, then (if any strip straddles an
-  // octant boundary, or has its halo columns apart) the others, in a second
-  // launch over the same grid in which the uniform strips return at once
-  hipLaunchKernelGGL((step_strip_kernel<2, false>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo,
-                     gh, chunk_rows, strips, order);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (T.n_mixed > 0 || T.nth % 2 != 0) {
-    hipLaunchKernelGGL((step_strip_kernel<2, true>), dim3(blocks), dim3(2 * WAVE), 0, s, T, fi, fo,
-                       gh, chunk_rows, strips, order);
-    e = hipGetLastError();
+  switch (T.scheme) {
+    case SCH_WB: return launch_strip_sch<SCH_WB>(T, fi, fo, gh, chunk_rows, strips, order, blocks, s);
+    case SCH_UPWIND2:
+      return launch_strip_sch<SCH_UPWIND2>(T, fi, fo, gh, chunk_rows, strips, order, blocks, s);
+    default: return launch_strip_sch<SCH_MWB>(T, fi, fo, gh, chunk_rows, strips, order, blocks, s);
   }
-  return e;
 }
 
 template bool strip_supported<float>(const Tables&);

@@ -1,7 +1,8 @@
 // Strip kernel of the combined-scheme step (Eq. combined_scheme) for FP64
-// storage, full annulus, MWB scheme.  A workgroup owns a strip of 64 theta
-// columns (one per lane; n_theta a multiple of 64) and marches in r over a
-// chunk of rows.  Four wavefronts share the strip, wave W owning the direction
+// storage, full annulus, MWB scheme (and the two upwind schemes it is
+// compared with, Warming-Beam and second-order upwind).  A workgroup owns a
+// strip of 64 theta columns (one per lane; n_theta a multiple of 64) and
+// marches in r over a chunk of rows.  Four wavefronts share the strip, wave W owning the direction
 // pair (W, W + 4): the eight velocities (k, W) and (k, W + 4), k = 1..4, and
 // wave 0 also the rest velocity.  For each owned velocity a wave keeps six
 // rows in registers, i-2 .. i+3 at row i: the radial stencil of either upwind
@@ -14,7 +15,7 @@
 // partials meet in LDS (one barrier per row, double-buffered by row parity),
 // and every wave builds the node's equilibrium from their fixed-order sum
 // (combine_partials, eq_setup) and updates its own velocities with the same
-// arithmetic as the node kernel (relax_pair, courant, mwb_update), so both
+// arithmetic as the node kernel (relax_pair, courant, the scheme's terms), so both
 // kernels give the same FP64 result bit for bit.  Azimuthal neighbours come
 // from the adjacent lanes (ds_bpermute of the centre row); the two columns
 // beyond each end of the strip come from a halo read one row ahead with one
@@ -77,7 +78,7 @@ __device__ inline double pick(uint64_t m, double a, double b) {
   return __builtin_bit_cast(double, (__builtin_bit_cast(uint64_t, a) & m) | (__builtin_bit_cast(uint64_t, b) & ~m));
 }
 
-template <int W>
+template <int W, int SCH>
 __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i0, int i1,
                                  double* lds) {
   constexpr int d4 = W;
@@ -191,7 +192,8 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
           const double g1 = __shfl(H1, eb[h] + v), g2 = __shfl(H2, eb[h] + v);
           const double u1t = e1[h] ? g1 : z1;
           const double u2t = e1[h] ? g2 : (e2[h] ? g1 : z2);
-          const double res = mwb_update<double>(rel[h], c, aCr, Kr, u1r, u2r, aCt, Kt, u1t, u2t);
+          const double res = scheme_update_d<SCH, double>(rel[h], aCr, Kr, c - u1r, u1r - u2r, aCt, Kt,
+                                                           c - u1t, u1t - u2t);
           __builtin_nontemporal_store(res, X.out + s64_q<W>(v) * X.plane + c0);
         }
       }
@@ -205,6 +207,7 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
   }
 }
 
+template <int SCH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 step_strip64_kernel(Tables T, const double* __restrict__ f, double* __restrict__ out,
                     const double* __restrict__ ghost, int chunk, int xcd_order) {
@@ -217,18 +220,19 @@ step_strip64_kernel(Tables T, const double* __restrict__ f, double* __restrict__
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const S64Ctx X{f, out, ghost, (size_t)T.nr * T.nth, T.nr, T.nth, j0 + lane, lane};
   switch (w) {
-    case 0: s64_march<0>(T, X, j0, i0, i1, lds); break;
-    case 1: s64_march<1>(T, X, j0, i0, i1, lds); break;
-    case 2: s64_march<2>(T, X, j0, i0, i1, lds); break;
-    default: s64_march<3>(T, X, j0, i0, i1, lds);
+    case 0: s64_march<0, SCH>(T, X, j0, i0, i1, lds); break;
+    case 1: s64_march<1, SCH>(T, X, j0, i0, i1, lds); break;
+    case 2: s64_march<2, SCH>(T, X, j0, i0, i1, lds); break;
+    default: s64_march<3, SCH>(T, X, j0, i0, i1, lds);
   }
 }
 
 }  // namespace
 
 bool strip64_supported(const Tables& T) {
-  // full annulus, MWB, whole strips
-  return T.nf == ND && T.scheme == SCH_MWB && T.nth >= WAVE && T.nth % WAVE == 0;
+  // full annulus, whole strips, the upwind schemes (not Lax-Wendroff, whose
+  // downwind neighbour the ring does not hold)
+  return T.nf == ND && T.scheme != SCH_LW && T.nth >= WAVE && T.nth % WAVE == 0;
 }
 
 hipError_t launch_step_strip64(const Tables& T, const void* f, void* out, const void* ghost,
@@ -238,8 +242,16 @@ hipError_t launch_step_strip64(const Tables& T, const void* f, void* out, const 
   while (tune.chunk <= 0 && chunk > 8 && (long)strips * ((T.nr + chunk - 1) / chunk) < 4096) chunk /= 2;
   const int chunks = (T.nr + chunk - 1) / chunk;
   const int order = tune.order < 0 ? 1 : tune.order;
-  hipLaunchKernelGGL(step_strip64_kernel, dim3(strips * chunks), dim3(S64_WAVES * WAVE), 0, s, T,
-                     (const double*)f, (double*)out, (const double*)ghost, chunk, order);
+  const dim3 grid(strips * chunks), block(S64_WAVES * WAVE);
+  const double* fi = (const double*)f;
+  const double* gh = (const double*)ghost;
+  double* fo = (double*)out;
+  if (T.scheme == SCH_WB)
+    hipLaunchKernelGGL((step_strip64_kernel<SCH_WB>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
+  else if (T.scheme == SCH_UPWIND2)
+    hipLaunchKernelGGL((step_strip64_kernel<SCH_UPWIND2>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
+  else
+    hipLaunchKernelGGL((step_strip64_kernel<SCH_MWB>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
   return hipGetLastError();
 }
 
