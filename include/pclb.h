@@ -77,9 +77,9 @@ enum {
  * its strips of 64 columns that straddle an octant boundary theta = m pi/4
  * (none when n_theta is a multiple of 512) run in a second launch of a
  * variant that selects upwind sides per lane.  Its double form runs double
- * states of the full annulus with an upwind scheme and n_theta a multiple of
- * 64.  Everything else (sectors, Lax-Wendroff, other grids) runs on the node
- * kernel, whatever is asked.  The
+ * states of the full annulus with any scheme and n_theta a multiple of 64.
+ * Everything else (sectors, float Lax-Wendroff, other grids) runs on the
+ * node kernel, whatever is asked.  The
  * double and triple octagon have kernels of their own: a strip form for the
  * double octagon and for float states of the triple octagon on the full
  * annulus with the MWB scheme and n_theta a multiple of 64 (chosen as above),
@@ -94,10 +94,10 @@ enum {
 };
 
 /* Convection scheme (pclb_config.scheme): the paper's MWB scheme and the three
- * it is compared with (Sec. II.B; Sec. III.A, Figs. 5 and 6).  MWB,
- * Warming-Beam and second-order upwind run on the strip kernels (Lax-Wendroff,
- * whose stencil reaches downwind, on the node kernel); only MWB has an
- * adjoint. */
+ * it is compared with (Sec. II.B; Sec. III.A, Figs. 5 and 6).  All run on
+ * the strip kernels except Lax-Wendroff for float octagon states, whose
+ * stencil reaches downwind beyond what that kernel's ring holds (it runs on
+ * the node kernel); only MWB has an adjoint. */
 enum {
   PCLB_SCHEME_MWB = 0,     /* Eq. MWB Scheme with S(eta) = (|eta| - 1) / (|eta| + 1) */
   PCLB_SCHEME_WB = 1,      /* Warming-Beam, Eq. WB_Scheme_1 */

@@ -469,9 +469,10 @@ __global__ void __launch_bounds__(DIAG_BLOCK) models_diag_kernel(Tables T, const
 }
 
 // ---------------------------------------------------------------------------
-// Strip form of the step (full annulus, MWB scheme, n_theta a multiple of
-// 64), the design of the octagon's FP64 strip kernel for N_i/2 direction
-// pairs: a workgroup of N_i/2 wavefronts owns a strip of 64 theta columns
+// Strip form of the step (full annulus, n_theta a multiple of 64, every
+// convection scheme: the ring holds both radial sides of a node and the halo
+// both azimuthal ones, so Lax-Wendroff's downwind neighbour is at hand), the
+// design of the octagon's FP64 strip kernel for N_i/2 direction pairs: a workgroup of N_i/2 wavefronts owns a strip of 64 theta columns
 // (one per lane) and marches in r over a chunk of rows; wave W owns the pair
 // (W, W + N_i/2), eight velocities, and wave 0 also the rest velocity.  Each
 // owned velocity keeps a ring of MS_RING rows in registers: six (i-2 .. i+3
@@ -504,7 +505,7 @@ __device__ inline double ms_pick(uint64_t m, double a, double b) {
 
 // d: this wave's direction pair (wave-uniform; one copy of the code serves
 // every wave, so that no wave holds another's values)
-template <class R, int NI, int MS_RING>
+template <class R, int NI, int MS_RING, int SCH>
 __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __restrict__ out,
                                 const R* __restrict__ ghost, int d, int j0, int i0, int i1,
                                 double* lds) {
@@ -520,8 +521,8 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
   const double e = T.e, ome = 1.0 - T.e;
   // per member h (direction d, then d + N_i/2, whose components are negated)
   uint64_t rm[2];
-  int a1[2], a2[2], eb[2];
-  bool e1[2], e2[2];
+  int a1[2], a2[2], eb[2], dn[2], ebd[2];
+  bool e1[2], e2[2], ed[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const double svr = h ? -vr : vr, svt = h ? -vt : vt;
@@ -533,6 +534,11 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
     eb[h] = tb ? 0 : 8;
     e1[h] = tb ? lane == 0 : lane == 63;
     e2[h] = tb ? lane == 1 : lane == 62;
+    // the downwind neighbour (Lax-Wendroff only): the other adjacent lane,
+    // the halo of the other side at the strip's downwind end
+    dn[h] = (lane - sc) & 63;
+    ebd[h] = tb ? 8 : 0;
+    ed[h] = tb ? lane == 63 : lane == 0;
   }
   const bool left_lane = (lane & 15) < 8;
   auto load = [&](int v, int row) -> R {
@@ -625,8 +631,14 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
           const R g1 = __shfl(H1, eb[h] + v), g2 = __shfl(H2, eb[h] + v);
           const R u1t = e1[h] ? g1 : z1;
           const R u2t = e1[h] ? g2 : (e2[h] ? g1 : z2);
-          const R tr = conv_term<SCH_MWB, R>(aCr, Kr, c, u1r, u2r, c);
-          const R tt = conv_term<SCH_MWB, R>(aCt, Kt, c, u1t, u2t, c);
+          R w1r = c, w1t = c;
+          if constexpr (SCH == SCH_LW) {
+            w1r = ms_pick(rm[h], slot(3, v), slot(1, v));
+            const R zd = __shfl(c, dn[h]), gd = __shfl(H1, ebd[h] + v);
+            w1t = ed[h] ? gd : zd;
+          }
+          const R tr = conv_term<SCH, R>(aCr, Kr, c, u1r, u2r, w1r);
+          const R tt = conv_term<SCH, R>(aCt, Kt, c, u1t, u2t, w1t);
           out[qv(v) * plane + c0] = (R)((rel[h] - (double)tr) - (double)tt);
         }
       });
@@ -640,7 +652,7 @@ __device__ inline void ms_march(const Tables& T, const R* __restrict__ f, R* __r
   }
 }
 
-template <class R, int NI, int RING>
+template <class R, int NI, int RING, int SCH>
 __global__ void __launch_bounds__(64 * (NI / 2))
 models_strip_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
                     const R* __restrict__ ghost, int chunk) {
@@ -650,8 +662,8 @@ models_strip_kernel(Tables T, const R* __restrict__ f, R* __restrict__ out,
   const int strip_i = item % nstrip, ck = item / nstrip;
   const int j0 = strip_i * 64;
   const int i0 = ck * chunk, i1 = min(i0 + chunk, T.nr);
-  ms_march<R, NI, RING>(T, f, out, ghost, __builtin_amdgcn_readfirstlane(threadIdx.x / 64), j0, i0, i1,
-                        lds);
+  ms_march<R, NI, RING, SCH>(T, f, out, ghost, __builtin_amdgcn_readfirstlane(threadIdx.x / 64), j0, i0,
+                             i1, lds);
 }
 
 }  // namespace
@@ -690,8 +702,29 @@ void launch_models_step_ni(const Tables& T, dim3 grid, const R* f, R* out, const
 // registers each: with a five-row ring (the look-ahead row issued one row
 // before its first use) the float form does; the double form spills.
 bool models_strip_supported(const Tables& T, int ni, int precision) {
-  return (ni == 16 || (ni == 24 && precision == 32)) && T.nf == ni && T.scheme == SCH_MWB &&
-         T.nth >= 64 && T.nth % 64 == 0;
+  // every scheme: the ring holds both radial sides and the halo both
+  // azimuthal ones
+  return (ni == 16 || (ni == 24 && precision == 32)) && T.nf == ni && T.nth >= 64 && T.nth % 64 == 0;
+}
+
+template <class R, int NI, int RING>
+void launch_models_strip_sch(const Tables& T, dim3 grid, const R* f, R* out, const R* gh, int chunk,
+                             hipStream_t s) {
+  const dim3 block(64 * (NI / 2));
+  switch (T.scheme) {
+    case SCH_WB:
+      hipLaunchKernelGGL((models_strip_kernel<R, NI, RING, SCH_WB>), grid, block, 0, s, T, f, out, gh, chunk);
+      break;
+    case SCH_LW:
+      hipLaunchKernelGGL((models_strip_kernel<R, NI, RING, SCH_LW>), grid, block, 0, s, T, f, out, gh, chunk);
+      break;
+    case SCH_UPWIND2:
+      hipLaunchKernelGGL((models_strip_kernel<R, NI, RING, SCH_UPWIND2>), grid, block, 0, s, T, f, out, gh,
+                         chunk);
+      break;
+    default:
+      hipLaunchKernelGGL((models_strip_kernel<R, NI, RING, SCH_MWB>), grid, block, 0, s, T, f, out, gh, chunk);
+  }
 }
 
 template <class R>
@@ -704,11 +737,9 @@ hipError_t launch_models_step(const Tables& T, int ni, const void* f, void* out,
     while (tune.chunk <= 0 && chunk > 8 && (long)strips * ((T.nr + chunk - 1) / chunk) < 4096) chunk /= 2;
     const dim3 grid(strips * ((T.nr + chunk - 1) / chunk));
     if (ni == 16)
-      hipLaunchKernelGGL((models_strip_kernel<R, 16, 6>), grid, dim3(64 * 8), 0, s, T, (const R*)f,
-                         (R*)out, (const R*)ghost, chunk);
+      launch_models_strip_sch<R, 16, 6>(T, grid, (const R*)f, (R*)out, (const R*)ghost, chunk, s);
     else if constexpr (prec == 32)
-      hipLaunchKernelGGL((models_strip_kernel<R, 24, 5>), grid, dim3(64 * 12), 0, s, T, (const R*)f,
-                         (R*)out, (const R*)ghost, chunk);
+      launch_models_strip_sch<R, 24, 5>(T, grid, (const R*)f, (R*)out, (const R*)ghost, chunk, s);
     return hipGetLastError();
   }
   const dim3 grid((T.nth + 255) / 256, T.nr);

@@ -1,6 +1,6 @@
 // Strip kernel of the combined-scheme step (Eq. combined_scheme) for FP64
-// storage, full annulus, MWB scheme (and the two upwind schemes it is
-// compared with, Warming-Beam and second-order upwind).  A workgroup owns a
+// storage, full annulus, MWB scheme (and the three schemes it is compared
+// with: Warming-Beam, Lax-Wendroff and second-order upwind).  A workgroup owns a
 // strip of 64 theta columns (one per lane; n_theta a multiple of 64) and
 // marches in r over a chunk of rows.  Four wavefronts share the strip, wave W owning the direction
 // pair (W, W + 4): the eight velocities (k, W) and (k, W + 4), k = 1..4, and
@@ -92,8 +92,8 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
   // side (0: left pairs, 8: right pairs), and whether this lane's u1 lies
   // beyond the strip (e1) or its u2 is the first column beyond it (e2)
   uint64_t rm[2];
-  int a1[2], a2[2], eb[2];
-  bool e1[2], e2[2];
+  int a1[2], a2[2], eb[2], dn[2], ebd[2];
+  bool e1[2], e2[2], ed[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     rm[h] = ((G.rback >> (d4 + 4 * h)) & 1u) ? ~0ull : 0ull;
@@ -104,6 +104,11 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
     eb[h] = tb ? 0 : 8;
     e1[h] = tb ? lane == 0 : lane == 63;
     e2[h] = tb ? lane == 1 : lane == 62;
+    // the downwind neighbour (Lax-Wendroff only): the other adjacent lane,
+    // the halo of the other side at the strip's downwind end
+    dn[h] = (lane - sc) & 63;
+    ebd[h] = tb ? 8 : 0;
+    ed[h] = tb ? lane == 63 : lane == 0;
   }
   const bool left_lane = (lane & 15) < 8;   // lanes holding a left halo pair
   // the ring: S[s][v] holds row (i - 2 + s) at slot (u + s) mod 6 of row i = ib + u
@@ -192,8 +197,18 @@ __device__ inline void s64_march(const Tables& T, const S64Ctx& X, int j0, int i
           const double g1 = __shfl(H1, eb[h] + v), g2 = __shfl(H2, eb[h] + v);
           const double u1t = e1[h] ? g1 : z1;
           const double u2t = e1[h] ? g2 : (e2[h] ? g1 : z2);
-          const double res = scheme_update_d<SCH, double>(rel[h], aCr, Kr, c - u1r, u1r - u2r, aCt, Kt,
-                                                           c - u1t, u1t - u2t);
+          double res;
+          if constexpr (SCH == SCH_LW) {
+            const double w1r = pick(rm[h], slot(3, v), slot(1, v));
+            const double zd = __shfl(c, dn[h]), gd = __shfl(H1, ebd[h] + v);
+            const double w1t = ed[h] ? gd : zd;
+            const double tr = conv_term<SCH_LW, double>(aCr, Kr, c, u1r, u2r, w1r);
+            const double tt = conv_term<SCH_LW, double>(aCt, Kt, c, u1t, u2t, w1t);
+            res = (rel[h] - tr) - tt;
+          } else {
+            res = scheme_update_d<SCH, double>(rel[h], aCr, Kr, c - u1r, u1r - u2r, aCt, Kt, c - u1t,
+                                               u1t - u2t);
+          }
           __builtin_nontemporal_store(res, X.out + s64_q<W>(v) * X.plane + c0);
         }
       }
@@ -230,9 +245,9 @@ step_strip64_kernel(Tables T, const double* __restrict__ f, double* __restrict__
 }  // namespace
 
 bool strip64_supported(const Tables& T) {
-  // full annulus, whole strips, the upwind schemes (not Lax-Wendroff, whose
-  // downwind neighbour the ring does not hold)
-  return T.nf == ND && T.scheme != SCH_LW && T.nth >= WAVE && T.nth % WAVE == 0;
+  // full annulus, whole strips, every scheme (the ring holds both radial
+  // sides and the halo both azimuthal ones)
+  return T.nf == ND && T.nth >= WAVE && T.nth % WAVE == 0;
 }
 
 hipError_t launch_step_strip64(const Tables& T, const void* f, void* out, const void* ghost,
@@ -250,6 +265,8 @@ hipError_t launch_step_strip64(const Tables& T, const void* f, void* out, const 
     hipLaunchKernelGGL((step_strip64_kernel<SCH_WB>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
   else if (T.scheme == SCH_UPWIND2)
     hipLaunchKernelGGL((step_strip64_kernel<SCH_UPWIND2>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
+  else if (T.scheme == SCH_LW)
+    hipLaunchKernelGGL((step_strip64_kernel<SCH_LW>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
   else
     hipLaunchKernelGGL((step_strip64_kernel<SCH_MWB>), grid, block, 0, s, T, fi, fo, gh, chunk, order);
   return hipGetLastError();

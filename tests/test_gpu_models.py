@@ -214,6 +214,31 @@ def test_strip_form_bitwise_equals_node_form(ni, shape):
 
 
 @pytest.mark.parametrize("ni", [16, 24])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+def test_strip_form_schemes_bitwise_equal_node_form(ni, scheme):
+    """The comparison schemes on the strip form (Lax-Wendroff's downwind
+    neighbours from the other side of the ring and the other halo) give the
+    per-node form's result bit for bit; chunks of 1 and 5 rows and the
+    default."""
+    from paper_1302_7104_amd import _native as N
+    from paper_1302_7104_amd.sim import Sim
+    P, F = problem(ni, ni, 13, 192, BCS[2], 14)
+    for prec in ((32, 64) if ni == 16 else (32,)):
+        ref = Sim(P, precision=prec, kernel=N.KERNEL_NODE, scheme=scheme)
+        ref.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+        ref.step(4)
+        want = ref.state.cpu().numpy()
+        ref.close()
+        for chunk in (0, 1, 5):
+            s = Sim(P, precision=prec, kernel=N.KERNEL_STRIP, strip_chunk=chunk, scheme=scheme)
+            s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+            s.step(4)
+            got = s.state.cpu().numpy()
+            s.close()
+            assert np.array_equal(got, want), (ni, scheme, prec, chunk)
+
+
+@pytest.mark.parametrize("ni", [16, 24])
 def test_strip_form_parity(ni):
     """The strip kernel asked for on a grid the strip form takes (n_theta =
     256: four strips) against the oracle: the strip form for the double

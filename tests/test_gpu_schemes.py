@@ -66,13 +66,14 @@ def test_scheme_step_parity(scheme, relax):
         assert node_err(got, want) <= NODE_TOL[prec], node_err(got, want)
 
 
-@pytest.mark.parametrize("scheme", [1, 3])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
 @pytest.mark.parametrize("shape", [(21, 256), (9, 130)])
-def test_upwind_schemes_on_the_strip_kernels_equal_the_node_kernel(scheme, shape):
-    """Warming-Beam and second-order upwind on the strip kernels (FP32; FP64
-    where n_theta is a multiple of 64) give the node kernel's result bit for
-    bit, for chunks of 1, 5 and 64 rows and the default, with walls and
-    inflow at the two sides: the same stencil, differences and rounding."""
+def test_schemes_on_the_strip_kernels_equal_the_node_kernel(scheme, shape):
+    """The comparison schemes on the strip kernels give the node kernel's
+    result bit for bit, for chunks of 1, 5 and 64 rows and the default, with
+    walls and inflow at the two sides: Warming-Beam and second-order upwind
+    on the FP32 kernel and, where n_theta is a multiple of 64, all three on
+    the FP64 kernel (the FP32 kernel leaves Lax-Wendroff to the node kernel)."""
     from paper_1302_7104_amd import _native as N
     nr, nth = shape
     P, F = W.smooth_random(nr, nth, seed=23, amp=0.05, bc=(W.WALL, W.INFLOW),
@@ -91,9 +92,10 @@ def test_upwind_schemes_on_the_strip_kernels_equal_the_node_kernel(scheme, shape
             s.close()
 
 
-def test_lax_wendroff_keeps_the_node_kernel():
-    """Lax-Wendroff's stencil reaches downwind, which the strip kernels' rings
-    do not hold: asked for the strip kernel it runs on the node kernel."""
+def test_lax_wendroff_keeps_the_node_kernel_in_fp32():
+    """Lax-Wendroff's stencil reaches downwind, which the FP32 strip kernel's
+    ring does not hold: asked for the strip kernel it runs on the node
+    kernel."""
     from paper_1302_7104_amd import _native as N
     P, F = W.kelvin_helmholtz(16, 512, 3)
     outs = []
