@@ -552,6 +552,24 @@ def test_evolve_checkpointing_matches_stored_trajectory():
     assert torch.equal(x2.grad, lam)
 
 
+def test_evolve_keeping_every_state_checks_device_memory():
+    """ckpt = 0 keeps n + 1 states: asked for more than the device holds it
+    raises before allocating any of them; a negative ckpt is refused."""
+    from paper_1302_7104_amd.sim import Evolve
+    P, F = W.richtmyer_meshkov(32, 96, 3)
+    s = sim_of(P, 64)
+    s.init_state(F["rho"], F["ur"], F["ut"], F["T"])
+    x = s.state.clone().requires_grad_(True)
+    free, _ = torch.cuda.mem_get_info(s.device)
+    n = int(2 * free // (s.state.numel() * s.state.element_size()))
+    before = torch.cuda.memory_allocated(s.device)
+    with pytest.raises(MemoryError, match="ckpt > 0"):
+        Evolve.apply(s, x, n, 0)
+    assert torch.cuda.memory_allocated(s.device) == before
+    with pytest.raises(ValueError):
+        Evolve.apply(s, x, 3, -1)
+
+
 def test_fd_matches_fp64_adjoint_gradient():
     """dJ/da_k (J = sum_band rho^2 r dr dtheta) of the Richtmyer-Meshkov
     recipe on the 1024 x 2048 adjoint grid after 20 steps: the FP64 adjoint
